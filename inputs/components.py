@@ -1,0 +1,69 @@
+"""Pure-component property tables used to build synthetic workloads.
+
+Data only: critical temperature Tc [K], critical pressure pc [bar], acentric
+factor omega [-] and molar mass M [g/mol].  No thermodynamic arithmetic lives
+here; both the CPU oracle and the GPU front end read these tables.
+"""
+from collections import namedtuple
+
+Component = namedtuple("Component", "name Tc pc omega M")
+
+# Paper, Section III, Table I (properties used in the LBM simulations).
+TABLE_I = {
+    "CO2": Component("CO2", 304.39, 73.843, 0.2667, 44.010),
+    "C1": Component("C1", 190.74, 45.947, 0.0104, 16.043),
+    "C2": Component("C2", 305.51, 48.711, 0.0979, 30.070),
+    "C3": Component("C3", 370.03, 42.472, 0.1522, 44.097),
+    "iC4": Component("iC4", 408.03, 36.397, 0.1852, 58.123),
+    "C4": Component("C4", 425.34, 37.963, 0.1995, 58.123),
+    "iC5": Component("iC5", 460.61, 33.812, 0.2280, 72.150),
+    "C5": Component("C5", 469.89, 33.688, 0.2514, 72.150),
+    "C6": Component("C6", 507.56, 30.123, 0.2994, 86.177),
+    "C7+": Component("C7+", 617.78, 21.043, 0.4898, 142.285),
+}
+
+# Paper, Section III.D, Table V (three-phase case; slightly different values).
+TABLE_V = {
+    "CO2": Component("CO2", 304.20, 73.75, 0.2250, 44.010),
+    "C1": Component("C1", 190.60, 45.99, 0.0080, 16.043),
+    "C4": Component("C4", 425.20, 37.99, 0.1930, 58.123),
+}
+
+# Three-component droplet system of the 64x64 droplet workload (textbook
+# critical constants; molar masses from Table I).
+DROPLET_3 = [
+    Component("C1", 190.6, 45.99, 0.011, 16.043),
+    Component("C3", 369.8, 42.48, 0.152, 44.097),
+    Component("nC5", 469.7, 33.70, 0.251, 72.150),
+]
+
+# n-alkane series C1..C10 for the ten-component spinodal workload.  C1-C6 are
+# Table I rows (C4 = n-butane, C5 = n-pentane); nC7-nC9 are standard
+# handbook critical constants (not in the paper); nC10 is the Table I "C7+"
+# row, whose molar mass is that of n-decane.
+N_ALKANES = [
+    TABLE_I["C1"], TABLE_I["C2"], TABLE_I["C3"], TABLE_I["C4"], TABLE_I["C5"],
+    TABLE_I["C6"],
+    Component("nC7", 540.2, 27.40, 0.350, 100.204),
+    Component("nC8", 568.7, 24.90, 0.399, 114.231),
+    Component("nC9", 594.6, 22.90, 0.445, 128.258),
+    Component("nC10", 617.78, 21.043, 0.4898, 142.285),
+]
+
+# Ternary used by the batched composition sweep: C1 / C3 / nC10.
+TERNARY_C1_C3_C10 = [TABLE_I["C1"], TABLE_I["C3"], N_ALKANES[9]]
+
+# Paper, Table II: components, temperature [K], pressure [bar] per case.
+TABLE_II = {
+    1: (["C1"], 177.24, 30.02),
+    2: (["C1", "C2"], 215.00, 32.00),
+    3: (["C1", "C2", "C3"], 250.00, 35.00),
+    4: (["C1", "C2", "C3", "C4"], 300.00, 40.00),
+    5: (["C1", "C2", "C3", "C4", "C5"], 350.00, 45.00),
+    6: (["C1", "C2", "C3", "C4", "C5", "C6"], 400.00, 50.00),
+}
+
+
+def table_ii_components(case):
+    names, T, p = TABLE_II[case]
+    return [TABLE_I[n] for n in names], T, p

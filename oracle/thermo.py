@@ -1,0 +1,358 @@
+"""Peng-Robinson thermodynamics for the CPU oracle (FP64, plain NumPy).
+
+TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the CPU-baseline
+leg of the benchmark may import anything under ``oracle/``; the GPU library
+never does, and this module shares no code with it.
+
+Contents, each following the paper's Section II.C unless noted:
+
+* ``alpha``                 -- the alpha(omega, T_r) correlation (two branches,
+                               split at omega = 0.49).
+* ``PRMixture``             -- a_i, b_i, alpha_i, vdW mixing rules Eq. (10)-(11),
+                               pressure Eq. (9), the cubic in Z obtained from
+                               Eq. (9), ln phi_i exactly as printed in Eq. (12).
+* ``LatticeUnits``          -- conversion to lattice units by fixing R, a, b and M
+                               of a reference component (Section III.A).
+* ``flash`` / ``maxwell``   -- textbook two-phase flash (Wilson start,
+                               Rachford-Rice, successive substitution) and the
+                               pure-component equal-area (equal-fugacity)
+                               construction.  The paper uses a flash but does not
+                               print its algorithm; these are written from the
+                               thermodynamics, not from any listing.
+"""
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+OMEGA_A = 0.457235529          # Section II.C, a_i prefactor
+OMEGA_B = 0.077796074          # Section II.C, b_i prefactor
+R_SI = 8.314462618             # J / (mol K)
+BAR = 1.0e5                    # Pa
+SQRT2 = math.sqrt(2.0)
+
+
+def alpha(omega, Tr):
+    """alpha_i(T) of Section II.C: first branch for omega <= 0.49."""
+    omega = np.asarray(omega, dtype=np.float64)
+    Tr = np.asarray(Tr, dtype=np.float64)
+    m_low = 0.374640 + 1.54226 * omega - 0.26992 * omega ** 2
+    m_high = (0.379642 + 1.48503 * omega - 0.164423 * omega ** 2
+              + 0.016666 * omega ** 3)
+    m = np.where(omega <= 0.49, m_low, m_high)
+    return (1.0 + m * (1.0 - np.sqrt(Tr))) ** 2
+
+
+class PRMixture:
+    """Peng-Robinson mixture at a fixed temperature, in any consistent units.
+
+    Parameters are per-component critical constants expressed in the same
+    unit system as ``R`` and ``T`` (SI by default).  ``kij`` is the binary
+    interaction matrix (the paper writes it delta_ij, Eq. (10)).
+    """
+
+    def __init__(self, Tc, pc, omega, T, kij=None, R=R_SI):
+        self.Tc = np.asarray(Tc, dtype=np.float64)
+        self.pc = np.asarray(pc, dtype=np.float64)
+        self.omega = np.asarray(omega, dtype=np.float64)
+        self.N = self.Tc.size
+        self.T = float(T)
+        self.R = float(R)
+        self.RT = self.R * self.T
+        self.a = OMEGA_A * self.R ** 2 * self.Tc ** 2 / self.pc
+        self.b = OMEGA_B * self.R * self.Tc / self.pc
+        self.alpha = alpha(self.omega, self.T / self.Tc)
+        self.aalpha = self.a * self.alpha
+        k = np.zeros((self.N, self.N)) if kij is None else np.asarray(kij, dtype=np.float64)
+        self.kij = k
+        # (a alpha)_ij = sqrt((a alpha)_i (a alpha)_j) (1 - delta_ij), Eq. (10)
+        self.aij = np.sqrt(np.outer(self.aalpha, self.aalpha)) * (1.0 - k)
+
+    # -- mixing rules -----------------------------------------------------
+    def mix(self, x):
+        """b_m (Eq. 11), S_i = sum_j x_j (a alpha)_ij and (a alpha)_m (Eq. 10)."""
+        x = np.asarray(x, dtype=np.float64)
+        bm = float(x @ self.b)
+        S = self.aij @ x
+        am = float(x @ S)
+        return bm, am, S
+
+    # -- Eq. (9) ----------------------------------------------------------
+    def pressure(self, x, v):
+        """p = RT/(v - b_m) - (a alpha)_m / (v^2 + 2 b_m v - b_m^2)."""
+        bm, am, _ = self.mix(x)
+        return self.RT / (v - bm) - am / (v * v + 2.0 * bm * v - bm * bm)
+
+    def pressure_rho(self, rho_molar):
+        """Pressure from a vector of component molar densities."""
+        rho_molar = np.asarray(rho_molar, dtype=np.float64)
+        rt = rho_molar.sum()
+        return self.pressure(rho_molar / rt, 1.0 / rt)
+
+    # -- cubic in Z ---------------------------------------------------------
+    def AB(self, x, p):
+        bm, am, _ = self.mix(x)
+        return am * p / self.RT ** 2, bm * p / self.RT
+
+    def z_roots(self, x, p):
+        """Real roots Z > B of Eq. (9) rewritten with v = Z RT / p, ascending.
+
+        Z^3 - (1 - B) Z^2 + (A - 3B^2 - 2B) Z - (AB - B^2 - B^3) = 0.
+        Each root is polished by Newton steps on the same polynomial.
+        """
+        A, B = self.AB(x, p)
+        c = [1.0, -(1.0 - B), A - 3.0 * B * B - 2.0 * B, -(A * B - B * B - B ** 3)]
+        r = np.roots(c)
+        out = []
+        for z in r:
+            if abs(z.imag) > 1e-7 * max(1.0, abs(z.real)):
+                continue
+            z = z.real
+            for _ in range(6):
+                f = ((z + c[1]) * z + c[2]) * z + c[3]
+                df = (3.0 * z + 2.0 * c[1]) * z + c[2]
+                if df == 0.0:
+                    break
+                z -= f / df
+            if z > B:
+                out.append(z)
+        return sorted(out), A, B
+
+    # -- Eq. (12) -----------------------------------------------------------
+    def ln_phi(self, x, Z, p):
+        """ln(f_i / (x_i p)) exactly in the printed form of Eq. (12)."""
+        x = np.asarray(x, dtype=np.float64)
+        bm, am, S = self.mix(x)
+        v = Z * self.RT / p
+        term1 = self.b / bm * (p * v / self.RT - 1.0)
+        term2 = -math.log((v - bm) * p / self.RT)
+        coef = am / (2.0 * SQRT2 * bm * self.RT)
+        bracket = self.b / bm - 2.0 / am * S
+        lnr = math.log((v + (1.0 + SQRT2) * bm) / (v + (1.0 - SQRT2) * bm))
+        return term1 + term2 + coef * bracket * lnr
+
+    def ln_fugacity(self, x, Z, p):
+        """ln f_i = ln(x_i p) + ln phi_i."""
+        return np.log(np.asarray(x) * p) + self.ln_phi(x, Z, p)
+
+    def ln_fugacity_rho(self, rho_molar):
+        """ln f_i at a state given by its molar densities (requires p > 0)."""
+        rho_molar = np.asarray(rho_molar, dtype=np.float64)
+        rt = rho_molar.sum()
+        x = rho_molar / rt
+        p = self.pressure(x, 1.0 / rt)
+        Z = p / (rt * self.RT)
+        return self.ln_fugacity(x, Z, p)
+
+    def phase(self, x, p, which):
+        roots, _, _ = self.z_roots(x, p)
+        if not roots:
+            raise ValueError("no admissible cubic root")
+        Z = roots[0] if which == "L" else roots[-1]
+        return Z, self.ln_phi(x, Z, p)
+
+
+# ---------------------------------------------------------------------------
+# Flash (textbook: Wilson, Rachford-Rice, successive substitution)
+# ---------------------------------------------------------------------------
+
+def wilson_K(mix, p):
+    """Wilson correlation: K_i = (pc_i / p) exp[5.373 (1 + w_i)(1 - Tc_i / T)]."""
+    return mix.pc / p * np.exp(5.373 * (1.0 + mix.omega) * (1.0 - mix.Tc / mix.T))
+
+
+def rachford_rice(z, K, tol=1e-15, maxit=200):
+    """Vapour fraction beta solving sum z_i (K_i - 1) / (1 + beta (K_i - 1)) = 0.
+
+    Safeguarded Newton on the open bracket (1/(1-K_max), 1/(1-K_min)); the
+    result may fall outside [0, 1] (negative flash).  Returns None when all
+    K_i are on one side of 1 (no root).
+    """
+    z = np.asarray(z, dtype=np.float64)
+    K = np.asarray(K, dtype=np.float64)
+    if K.max() <= 1.0 or K.min() >= 1.0:
+        return None
+    lo = 1.0 / (1.0 - K.max())
+    hi = 1.0 / (1.0 - K.min())
+    km1 = K - 1.0
+
+    def g(beta):
+        d = 1.0 + beta * km1
+        return float(np.sum(z * km1 / d)), float(-np.sum(z * km1 * km1 / (d * d)))
+
+    beta = 0.5 * (lo + hi)
+    if 0.0 < lo < 1.0 or 0.0 < hi < 1.0 or (lo < 0.5 < hi):
+        beta = min(max(0.5, lo + 1e-12), hi - 1e-12)
+    for _ in range(maxit):
+        f, df = g(beta)
+        if f > 0.0:
+            lo = beta
+        else:
+            hi = beta
+        step = -f / df if df != 0.0 else 0.0
+        nb = beta + step
+        if not (lo < nb < hi):
+            nb = 0.5 * (lo + hi)
+        if abs(nb - beta) <= tol * max(1.0, abs(nb)):
+            beta = nb
+            break
+        beta = nb
+    return beta
+
+
+@dataclass
+class FlashResult:
+    beta: float           # vapour mole fraction
+    x: np.ndarray         # liquid composition
+    y: np.ndarray         # vapour composition
+    ZL: float
+    ZV: float
+    rhoL: float           # liquid molar density (units of the mixture)
+    rhoV: float           # vapour molar density
+    iterations: int
+    converged: bool
+    two_phase: bool
+
+
+def flash(mix, z, p, K0=None, tol=1e-13, maxit=20000):
+    """Isothermal two-phase flash at (T, p, z) by successive substitution.
+
+    Stops when max |delta ln K| < tol.  ``two_phase`` is False when the
+    Rachford-Rice root is outside (0, 1) or K collapses to 1 (trivial
+    solution).
+    """
+    z = np.asarray(z, dtype=np.float64)
+    z = z / z.sum()
+    K = wilson_K(mix, p) if K0 is None else np.asarray(K0, dtype=np.float64).copy()
+    lnK = np.log(K)
+    converged = False
+    beta = None
+    x = y = z
+    ZL = ZV = float("nan")
+    it = 0
+    for it in range(1, maxit + 1):
+        beta = rachford_rice(z, K)
+        if beta is None:
+            break
+        x = z / (1.0 + beta * (K - 1.0))
+        y = K * x
+        x = x / x.sum()
+        y = y / y.sum()
+        ZL, lpl = mix.phase(x, p, "L")
+        ZV, lpv = mix.phase(y, p, "V")
+        lnK_new = lpl - lpv
+        d = np.max(np.abs(lnK_new - lnK))
+        lnK = lnK_new
+        K = np.exp(lnK)
+        if d < tol:
+            converged = True
+            break
+        if np.max(np.abs(lnK)) < 1e-8:
+            break
+    two = (converged and beta is not None and 0.0 < beta < 1.0
+           and np.max(np.abs(lnK)) > 1e-6)
+    rhoL = p / (ZL * mix.RT)
+    rhoV = p / (ZV * mix.RT)
+    return FlashResult(beta if beta is not None else float("nan"), x, y, ZL, ZV,
+                       rhoL, rhoV, it, converged, bool(two))
+
+
+def maxwell(mix, p0=None, tol=1e-14, maxit=200):
+    """Saturation state of a pure component: equal pressure and fugacity.
+
+    Newton on g(p) = ln phi_L(p) - ln phi_V(p) with dg/dp = (Z_L - Z_V) / p
+    (the pressure derivative of ln phi at fixed T is (Z - 1)/p).  Returns
+    (p_sat, rho_V, rho_L) in the mixture's units (molar densities).
+    """
+    assert mix.N == 1
+    x = np.ones(1)
+    p = float(wilson_K(mix, 1.0)[0]) if p0 is None else float(p0)
+    lo, hi = 0.0, float(mix.pc[0])
+    for _ in range(maxit):
+        roots, _, _ = mix.z_roots(x, p)
+        if len(roots) < 2 or roots[0] == roots[-1]:
+            # outside the three-root band: bisect toward it
+            Zs = roots[0] if roots else 1.0
+            if Zs > 0.3:        # only a vapour-like root: pressure too low
+                lo = p
+            else:
+                hi = p
+            p = 0.5 * (lo + hi) if hi > lo else p * 0.9
+            continue
+        ZL, ZV = roots[0], roots[-1]
+        g = float(mix.ln_phi(x, ZL, p)[0] - mix.ln_phi(x, ZV, p)[0])
+        if g > 0.0:            # liquid less stable: below saturation
+            lo = max(lo, p)
+        else:
+            hi = min(hi, p)
+        dg = (ZL - ZV) / p
+        pn = p - g / dg
+        if not (lo < pn < hi):
+            pn = 0.5 * (lo + hi)
+        if abs(pn - p) <= tol * p:
+            p = pn
+            break
+        p = pn
+    roots, _, _ = mix.z_roots(x, p)
+    ZL, ZV = roots[0], roots[-1]
+    return p, p / (ZV * mix.RT), p / (ZL * mix.RT)
+
+
+# ---------------------------------------------------------------------------
+# Lattice units (Section III.A: R, a, b and M of the reference component are
+# fixed; the same anchors recur in III.B, III.C and III.E)
+# ---------------------------------------------------------------------------
+
+class LatticeUnits:
+    """Scales between SI and lattice units anchored on one component.
+
+    With a_ref, b_ref and R fixed in lattice units, the reference component's
+    critical temperature and pressure in lattice units follow from
+    a = Omega_a R^2 Tc^2 / pc and b = Omega_b R Tc / pc.
+    """
+
+    def __init__(self, ref, a_lu=2.0 / 49.0, b_lu=2.0 / 21.0, R_lu=1.0, M_lu=1.0):
+        self.ref = ref
+        self.a_lu, self.b_lu, self.R_lu, self.M_lu = a_lu, b_lu, R_lu, M_lu
+        self.Tc_ref_lu = (a_lu / b_lu) * (OMEGA_B / OMEGA_A) / R_lu
+        self.pc_ref_lu = OMEGA_B * R_lu * self.Tc_ref_lu / b_lu
+        self.T_scale = ref.Tc / self.Tc_ref_lu                 # K per lu
+        self.p_scale = ref.pc * BAR / self.pc_ref_lu            # Pa per lu
+        b_ref_si = OMEGA_B * R_SI * ref.Tc / (ref.pc * BAR)
+        self.V_scale = b_ref_si / b_lu                          # m^3/mol per lu
+        self.M_scale = ref.M / M_lu                             # g/mol per lu
+
+    def T(self, T_K):
+        return T_K / self.T_scale
+
+    def p(self, p_Pa):
+        return p_Pa / self.p_scale
+
+    def rho_molar(self, rho_si):
+        """mol/m^3 -> lattice molar density."""
+        return np.asarray(rho_si) * self.V_scale
+
+    def rho_molar_si(self, rho_lu):
+        return np.asarray(rho_lu) / self.V_scale
+
+    def mixture(self, comps, T_K, kij=None):
+        """The PR mixture with every constant in lattice units."""
+        Tc = np.array([c.Tc for c in comps]) / self.T_scale
+        pc = np.array([c.pc * BAR for c in comps]) / self.p_scale
+        om = np.array([c.omega for c in comps])
+        return PRMixture(Tc, pc, om, self.T(T_K), kij, R=self.R_lu)
+
+    def molar_masses(self, comps):
+        return np.array([c.M for c in comps]) / self.M_scale
+
+
+def si_mixture(comps, T_K, kij=None):
+    """The PR mixture in SI units (Pa, m^3/mol)."""
+    return PRMixture([c.Tc for c in comps], [c.pc * BAR for c in comps],
+                     [c.omega for c in comps], T_K, kij)
+
+
+def mass_density_si(comps, rho_molar_si_vec):
+    """kg/m^3 of a phase from its component molar densities [mol/m^3]."""
+    M = np.array([c.M for c in comps]) * 1e-3
+    return float(np.dot(M, rho_molar_si_vec))

@@ -1,0 +1,134 @@
+"""Write ``inputs/phase_states.json``: the phase densities every synthetic
+workload starts from, computed by the oracle's own flash / Maxwell code.
+
+Run: ``python -m oracle.write_phase_states`` (from the repository root).
+Only ``oracle/`` and the seeded draws in ``inputs/`` are used; nothing comes
+from the GPU path.  All densities stored are lattice-unit MASS densities per
+component (rho_i = M_i rho~_i), in the lattice units of each workload's own
+anchor (its first component, a = 2/49, b = 2/21, R = 1, M = 1).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from inputs import components as C          # noqa: E402
+from inputs import fields as Fi             # noqa: E402
+from oracle import thermo as th             # noqa: E402
+from oracle.lbm import oracle_mixture       # noqa: E402
+
+BAR = th.BAR
+
+
+def two_phase_state(comps, T, p_bar, z, kij=None):
+    """Flash at (T, p, z) in lattice units; returns dict or None if one phase."""
+    om = oracle_mixture(comps, T, kij)
+    pr = om.pr
+    p_lu = om.units.p(p_bar * BAR)
+    if len(comps) == 1:
+        ps, rV, rL = th.maxwell(pr)
+        return dict(p_lu=ps, p_bar=ps * om.units.p_scale / BAR, beta=None, S_V=0.5,
+                    rho_V=list(om.M * rV), rho_L=list(om.M * rL),
+                    x=[1.0], y=[1.0])
+    r = th.flash(pr, z, p_lu)
+    if not r.two_phase:
+        return None
+    vV, vL = 1.0 / r.rhoV, 1.0 / r.rhoL
+    S_V = r.beta * vV / (r.beta * vV + (1.0 - r.beta) * vL)
+    rho_V = om.M * r.y * r.rhoV
+    rho_L = om.M * r.x * r.rhoL
+    # overall (lever-rule) molar density of the two-phase state
+    rho_tot = 1.0 / (r.beta * vV + (1.0 - r.beta) * vL)
+    return dict(p_lu=p_lu, p_bar=p_bar, beta=r.beta, S_V=S_V,
+                rho_V=list(rho_V), rho_L=list(rho_L), x=list(r.x), y=list(r.y),
+                rho_uniform=list(om.M * np.asarray(z) / np.sum(z) * rho_tot))
+
+
+def comp_list(comps):
+    return [c._asdict() for c in comps]
+
+
+def ternary_sweep(n_inst=256, seed=3):
+    """Seeded two-phase draws for the batched ternary sweep (C1/C3/nC10)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    comps = C.TERNARY_C1_C3_C10
+    out = []
+    tries = 0
+    while len(out) < n_inst and tries < 50000:
+        tries += 1
+        n = int(rng.integers(0, 13)) * 16 + 64          # 64..256 step 16
+        T = float(rng.uniform(250.0, 450.0))
+        p = float(rng.uniform(20.0, 150.0))
+        z = rng.dirichlet(np.ones(3))
+        st = two_phase_state(comps, T, p, z)
+        if st is None or not (0.1 <= st["S_V"] <= 0.9):
+            continue
+        if np.max(np.abs(np.array(st["x"]) - np.array(st["y"]))) < 0.05:
+            continue
+        st.update(n=n, T=T, p_bar_in=p, z=list(z))
+        out.append(st)
+    return out
+
+
+def serving_pool(n_req=160, seed=5):
+    """Seeded request pool for the serving stream (first N n-alkanes)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    tries = 0
+    while len(out) < n_req and tries < 100000:
+        tries += 1
+        N = int(rng.integers(2, 11))
+        three_d = bool(rng.uniform() < 0.2)
+        n = int(rng.integers(0, 5)) * 16 + 64 if three_d else int(rng.integers(0, 29)) * 16 + 64
+        T = float(rng.uniform(250.0, 450.0))
+        p = float(rng.uniform(20.0, 150.0))
+        z = rng.dirichlet(np.ones(N))
+        comps = C.N_ALKANES[:N]
+        st = two_phase_state(comps, T, p, z)
+        if st is None or not (0.2 <= st["S_V"] <= 0.8):
+            continue
+        if np.max(np.abs(np.array(st["x"]) - np.array(st["y"]))) < 0.05:
+            continue
+        st.update(N=N, lattice="D3Q19" if three_d else "D2Q9", n=n, T=T, p_bar_in=p,
+                  z=list(z), arrival_u=float(rng.uniform()))
+        out.append(st)
+    return out
+
+
+def main():
+    states = {}
+    # 64x64 three-component droplet: 250 K, 50 bar, z = (0.5, 0.25, 0.25)
+    st = two_phase_state(C.DROPLET_3, 250.0, 50.0, [0.5, 0.25, 0.25])
+    st.update(components=comp_list(C.DROPLET_3), T=250.0, z=[0.5, 0.25, 0.25])
+    states["droplet3"] = st
+    # flat-interface VLE, Table II cases 1-6, equimolar z
+    for case in range(1, 7):
+        comps, T, p = C.table_ii_components(case)
+        z = [1.0 / len(comps)] * len(comps)
+        st = two_phase_state(comps, T, p, z)
+        st.update(components=comp_list(comps), T=T, z=z)
+        states["vle%d" % case] = st
+    # ten-component n-alkane spinodal: 325 K, 150 bar, seeded kij in [0, 0.05)
+    kij = Fi.draw_kij(10, 0.0, 0.05, seed=4)
+    z = Fi.spinodal_z()
+    st = two_phase_state(C.N_ALKANES, 325.0, 150.0, z, kij)
+    st.update(components=comp_list(C.N_ALKANES), T=325.0, z=list(z),
+              kij=kij.tolist())
+    states["spinodal10"] = st
+    states["ternary_sweep"] = dict(components=comp_list(C.TERNARY_C1_C3_C10),
+                                   instances=ternary_sweep())
+    states["serving_pool"] = dict(components=comp_list(C.N_ALKANES),
+                                  requests=serving_pool())
+    path = Fi.PHASE_STATES
+    with open(path, "w") as f:
+        json.dump(states, f, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()
