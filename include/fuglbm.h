@@ -1,0 +1,180 @@
+/*
+ * fuglbm.h -- C ABI of the MI355X (gfx950) fugacity-based multicomponent
+ * lattice Boltzmann hot path.
+ *
+ * One step, for every lattice site r and component i (paper Section II):
+ *   rho_i = sum_a g_{a,i};  rt_i = rho_i / M_i                (molar density)
+ *   ln f_i from the Peng-Robinson EOS, Eq. (9)-(12), local in rt_1..rt_N
+ *   psi_i = RT ln f_i - sqrt(kappa_i) lap(sum_j sqrt(kappa_j) rt_j)
+ *           (Eq. (3)-(5) with the rank-one kappa_ij of Eq. (4), kappa_i of Eq. (6))
+ *   F_i = -rt_i grad(psi_i);  u = (sum_i sum_a e_a g_{a,i} + F/2) / rho
+ *   g_{a,i}(r + e_a, t+1) = g - (g - geq)/tau + (1 - 1/(2tau)) F_{a,i}
+ *           (Eq. (1a); equilibrium Eq. (1b) with rho^c = 0; forcing Eq. (1c))
+ * on a periodic D2Q9 or D3Q19 lattice, dt = dx = 1, cs^2 = 1/3.  grad and lap
+ * are the isotropic lattice stencils
+ *   grad phi = 3 sum_a w_a e_a (phi(r+e_a) - phi(r-e_a)) / 2,
+ *   lap  phi = 6 sum_a w_a (phi(r+e_a) - phi(r)).
+ *
+ * Conventions
+ *  - Every call returns fuglbm_status; nothing is thrown across the ABI.  On a
+ *    non-OK status fuglbm_last_error() returns a message for the calling
+ *    thread.
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *    device memory of the current device; hip_stream is a hipStream_t (NULL:
+ *    the null stream).
+ *  - Descriptors and host arrays are copied during the call; the library
+ *    never keeps a caller's host pointer.
+ *  - A mixture must outlive every simulation made from it.  Handles are not
+ *    thread-safe: use one handle from one thread at a time.
+ *  - Populations are stored component-major, g[i][a][site] with
+ *    site = x + nx*(y + ny*z), two buffers swapped every step.  FP32 storage
+ *    keeps g_{a,i} - rhobar_i*delta_{a0} in float, rhobar_i being the
+ *    per-component domain mean at init (FP64); arithmetic stays FP64.
+ */
+#ifndef FUGLBM_H
+#define FUGLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FUGLBM_MAX_COMP 16
+
+typedef enum {
+    FUGLBM_OK = 0,
+    FUGLBM_EINVAL = 1,        /* bad argument: null pointer, size, range, asymmetric kij, tau <= 1/2 */
+    FUGLBM_ENOMEM = 2,        /* device or host allocation failed, or dev_buf too small */
+    FUGLBM_EDEVICE = 3,       /* a HIP runtime call failed */
+    FUGLBM_EUNPHYSICAL = 4,   /* input field with rho_i <= 0, non-finite, or b_m*rt >= 1 */
+    FUGLBM_ENONFINITE = 5,    /* sticky: the device saw a non-finite or out-of-domain state */
+    FUGLBM_ESTATE = 6         /* call not valid in the handle's state (mixed lattice in a batch, ...) */
+} fuglbm_status;
+
+typedef enum { FUGLBM_D2Q9 = 0, FUGLBM_D3Q19 = 1 } fuglbm_lattice;
+typedef enum { FUGLBM_FP64 = 0, FUGLBM_FP32_STORAGE = 1 } fuglbm_precision;
+
+/* Device status bits (fuglbm_diag.status). */
+#define FUGLBM_ST_NONFINITE 1u   /* a non-finite ln f_i, density or population */
+#define FUGLBM_ST_COVOLUME  2u   /* 1 - b_m rt <= 0 (outside the EOS domain) */
+#define FUGLBM_ST_NEGATIVE  4u   /* some rt_i <= 0 */
+
+typedef struct fuglbm_mixture fuglbm_mixture;
+typedef struct fuglbm_sim fuglbm_sim;
+
+/* Physical description of a mixture (paper Table I units).  Lattice units
+ * are fixed by R, a and b of the reference component (paper Section III.A:
+ * R = 1, a = 2/49, b = 2/21, M = 1 for C1); kappa_i = kappa_ref a_i / a_ref
+ * (Eq. (6)-(8)). */
+typedef struct {
+    int32_t ncomp;                 /* 1..FUGLBM_MAX_COMP */
+    const double *Tc_K;            /* [ncomp] critical temperature, K */
+    const double *pc_bar;          /* [ncomp] critical pressure, bar */
+    const double *omega;           /* [ncomp] acentric factor */
+    const double *M_gmol;          /* [ncomp] molar mass, g/mol */
+    const double *kij;             /* [ncomp*ncomp] row-major, symmetric, zero diagonal;
+                                      NULL = all zero (delta_ij of Eq. (10)) */
+    double T_K;                    /* temperature (isothermal), K */
+    int32_t ref_comp;              /* anchor and kappa reference component */
+    double a_ref_lu, b_ref_lu, R_lu; /* 0 = defaults 2/49, 2/21, 1 */
+    double kappa_ref_lu;           /* kappa of the reference component, lattice units */
+    double tau;                    /* BGK relaxation time, > 1/2 (paper: 1) */
+} fuglbm_mixture_desc;
+
+/* Diagnostics (FP64 sums in a fixed order: bitwise reproducible). */
+typedef struct {
+    int64_t step;                  /* steps taken since init */
+    double mass[FUGLBM_MAX_COMP];  /* sum_r rho_i */
+    double momentum[3];            /* sum_r sum_i sum_a e_a g_{a,i} (populations' own momentum) */
+    double residual;               /* max_i sum_r |rho_i(t) - rho_i(t-K)| / (K sum_r rho_i(t)),
+                                      K = steps since the previous diagnostics call
+                                      (0 on the first call) */
+    uint32_t status;               /* OR of FUGLBM_ST_* bits seen since init */
+} fuglbm_diag;
+
+/* Build a mixture: unit conversion and every per-component constant in
+ * FP64 (a_i, b_i, alpha_i(T), (a alpha)_ij, sqrt kappa_i, M_i).
+ * Errors: EINVAL for null/out-of-range fields, non-positive Tc/pc/M/T,
+ * tau <= 1/2, asymmetric kij or a non-zero kij diagonal; ENOMEM. */
+fuglbm_status fuglbm_init_mixture(const fuglbm_mixture_desc *desc, fuglbm_mixture **out);
+
+/* Copy the lattice-unit constants into host array out[n]:
+ * [RT, then for each component b_i, (a alpha)_i, sqrt(kappa_i), M_i, then the
+ *  ncomp x ncomp matrix (a alpha)_ij row-major]; n must be >= 1 + 4N + N^2. */
+fuglbm_status fuglbm_lattice_constants(const fuglbm_mixture *mix, double *out, size_t n);
+
+void fuglbm_destroy_mixture(fuglbm_mixture *mix);
+
+/* Bytes of device memory one simulation needs (both population buffers and
+ * the library's workspace), i.e. the minimum size of a borrowed dev_buf. */
+size_t fuglbm_fields_bytes(int32_t ncomp, fuglbm_lattice lattice, fuglbm_precision prec,
+                           int32_t nx, int32_t ny, int32_t nz);
+
+/* Create a simulation and set g = geq(rho_i, u = 0) (g_0 = rho_i, others 0).
+ * rho: host [ncomp][nz][ny][nx] mass densities in lattice units.
+ * dev_buf: NULL = the library allocates; else a device buffer of at least
+ *   fuglbm_fields_bytes() bytes, 256-byte aligned, borrowed (the caller keeps
+ *   it alive until fuglbm_destroy_sim).
+ * Enqueued on hip_stream; rho is copied before return.
+ * Errors: EINVAL (sizes < 1, nz != 1 for D2Q9), EUNPHYSICAL (rho_i <= 0,
+ * non-finite, or b_m rt >= 1 somewhere), ENOMEM, EDEVICE. */
+fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice lattice,
+                                 fuglbm_precision prec, int32_t nx, int32_t ny, int32_t nz,
+                                 const double *rho, void *dev_buf, void *hip_stream,
+                                 fuglbm_sim **out);
+
+/* Enqueue nsteps steps on hip_stream (asynchronous; no host sync).  Returns
+ * the sticky ENONFINITE without launching if an earlier synchronising call
+ * saw a device status bit. */
+fuglbm_status fuglbm_step_n(fuglbm_sim *sim, int64_t nsteps, void *hip_stream);
+
+/* Advance count simulations by nsteps each with one launch per step for the
+ * whole set (D2Q9 simulations sharing ncomp and precision are packed into a
+ * single tile table; others fall back to their own launches).  Handles must
+ * be distinct.  Asynchronous on hip_stream. */
+fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count, int64_t nsteps,
+                               void *hip_stream);
+
+/* Synchronise and read macroscopic fields: rho_out host [ncomp][sites] (or
+ * NULL), u_out host [D][sites] force-corrected velocity (or NULL), diag (or
+ * NULL; as fuglbm_diagnostics).  Returns ENONFINITE if a status bit is set
+ * (the fields are still written). */
+fuglbm_status fuglbm_read_moments(fuglbm_sim *sim, double *rho_out, double *u_out,
+                                  fuglbm_diag *diag);
+
+/* Synchronise and compute mass, momentum, residual and status (see
+ * fuglbm_diag).  Keeps rho_i(t) as the snapshot for the next residual. */
+fuglbm_status fuglbm_diagnostics(fuglbm_sim *sim, fuglbm_diag *diag);
+
+/* Checkpoint / restore the raw populations, host [ncomp][Q][sites] FP64
+ * (FP32 storage is widened / rounded; the rest-direction offset is applied). */
+fuglbm_status fuglbm_read_populations(fuglbm_sim *sim, double *g_out);
+fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int64_t step);
+
+/* Launch tuning: kernel 0 = automatic, 1 = three-pass generic kernels,
+ * 2 = fused one-pass D2Q9 kernel; rows = output rows per fused work item
+ * (0 = automatic).  EINVAL for a kernel the simulation cannot use. */
+fuglbm_status fuglbm_set_tuning(fuglbm_sim *sim, int32_t kernel, int32_t rows);
+
+/* Query: Q, spatial dimension, sites, bytes moved per step by the
+ * algorithm (2 Q N s per site), and the kernel in use. */
+fuglbm_status fuglbm_sim_info(const fuglbm_sim *sim, int32_t *Q, int32_t *D, int64_t *sites,
+                              int64_t *alg_bytes_per_step, int32_t *kernel);
+
+/* Test hook: overwrite one population (component comp, direction a, site)
+ * in the current buffer with value; synchronous. */
+fuglbm_status fuglbm_poke_population(fuglbm_sim *sim, int32_t comp, int32_t a, int64_t site,
+                                     double value);
+
+void fuglbm_destroy_sim(fuglbm_sim *sim);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *fuglbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FUGLBM_H */

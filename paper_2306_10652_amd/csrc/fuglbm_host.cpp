@@ -1,0 +1,757 @@
+// Host side of the C ABI declared in include/fuglbm.h: lattice-unit
+// constants, buffer carving, launch tables, hipGraph replay, sticky errors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fuglbm.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+fuglbm_status fail(fuglbm_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+fuglbm_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return FUGLBM_EDEVICE;
+}
+
+#define HIP_TRY(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+constexpr double OMEGA_A = 0.457235529;  // PR attraction prefactor (Section II.C)
+constexpr double OMEGA_B = 0.077796074;  // PR co-volume prefactor
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int lattice_Q(int lat) { return lat == 0 ? 9 : 19; }
+int lattice_D(int lat) { return lat == 0 ? 2 : 3; }
+
+// Fused-kernel rows per work item: enough items to fill 256 CUs a few
+// times, rows >= 8, at most the grid height.
+int auto_rows(int nx, int ny) {
+    const int strips = (nx + FUSED_OUT - 1) / FUSED_OUT;
+    int rows = 64;
+    while (rows > 8 && (int64_t)strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
+    return std::min(rows, ny);
+}
+
+}  // namespace
+
+struct fuglbm_mixture {
+    int N;
+    double RT;
+    double b[FUG_MAXC], aa[FUG_MAXC], sqk[FUG_MAXC], M[FUG_MAXC];
+    double aij[FUG_MAXC * FUG_MAXC];
+    double tau;
+};
+
+// Layout of one simulation's device memory (offsets from base, 256-aligned).
+struct Carve {
+    size_t buf0, buf1, cst, status, rho, psi, s, j, u, snap, part, fsim, items, total;
+    int max_items;
+};
+
+static Carve carve(int N, int lat, bool fp32, int nx, int ny, int nz) {
+    Carve c{};
+    const int64_t ns = (int64_t)nx * ny * nz;
+    const int Q = lattice_Q(lat), D = lattice_D(lat);
+    const size_t pop = align256((size_t)N * Q * ns * (fp32 ? 4 : 8));
+    size_t o = 0;
+    c.buf0 = o; o += pop;
+    c.buf1 = o; o += pop;
+    c.cst = o; o += align256(sizeof(SimConst));
+    c.status = o; o += 256;
+    c.rho = o; o += align256((size_t)N * ns * 8);
+    c.psi = o; o += align256((size_t)N * ns * 8);
+    c.s = o; o += align256((size_t)ns * 8);
+    c.j = o; o += align256((size_t)D * ns * 8);
+    c.u = o; o += align256((size_t)D * ns * 8);
+    c.snap = o; o += align256((size_t)N * ns * 8);
+    c.part = o; o += align256((size_t)1024 * (2 * N + 3) * 8);
+    c.fsim = o; o += align256(sizeof(FusedSim));
+    c.max_items = 0;
+    if (lat == 0) {
+        const int strips = (nx + FUSED_OUT - 1) / FUSED_OUT;
+        c.max_items = strips * ((ny + 7) / 8) + 8;
+    }
+    c.items = o; o += align256((size_t)c.max_items * sizeof(FusedItem));
+    c.total = o;
+    return c;
+}
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    int steps = 0;
+    int kernel = 0;
+    int rows = 0;
+};
+
+struct fuglbm_sim {
+    const fuglbm_mixture *mix;
+    int lattice;
+    bool fp32;
+    int nx, ny, nz, N, Q, D;
+    int64_t ns;
+    char *base;
+    bool owned;
+    Carve cv;
+    void *buf[2];
+    int parity;            // buffer holding the current state
+    SimConst hc;           // host copy of the constant block
+    SimConst *dc;
+    uint32_t *status;
+    double *rho_f, *psi_f, *s_f, *j_f, *u_f, *snap, *part;
+    FusedSim *fsim;
+    FusedItem *items;
+    int nitems;
+    int kernel;            // 1 generic, 2 fused
+    int rows;
+    int64_t step;
+    int64_t snap_step;
+    bool have_snap;
+    uint32_t sticky;
+    hipStream_t last_stream;
+    GraphCache graph;
+};
+
+namespace {
+
+hipStream_t capture_stream() {
+    static hipStream_t s = nullptr;
+    if (!s) {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    }
+    return s;
+}
+
+fuglbm_status build_items(fuglbm_sim *s) {
+    std::vector<FusedItem> it;
+    const int strips = (s->nx + FUSED_OUT - 1) / FUSED_OUT;
+    const int rows = s->rows;
+    const int chunks = (s->ny + rows - 1) / rows;
+    // logical order: chunk-major (a band of rows across the full width)
+    std::vector<FusedItem> logical;
+    for (int c = 0; c < chunks; ++c)
+        for (int t = 0; t < strips; ++t)
+            logical.push_back({0, t * FUSED_OUT, c * rows, std::min(rows, s->ny - c * rows)});
+    // Workgroups are handed to the 8 XCDs round-robin; give XCD k the k-th
+    // contiguous slice of the logical order so neighbouring items (which
+    // re-read each other's halo) share that XCD's L2.
+    const int n = (int)logical.size();
+    const int per = (n + 7) / 8;
+    it.assign((size_t)per * 8, FusedItem{-1, 0, 0, 0});
+    for (int b = 0; b < per * 8; ++b) {
+        const int k = b % 8, q = b / 8;
+        const int li = k * per + q;
+        if (li < n) it[b] = logical[li];
+    }
+    if ((int)it.size() > s->cv.max_items) return fail(FUGLBM_EINVAL, "too many work items");
+    s->nitems = (int)it.size();
+    HIP_TRY(hipMemcpy(s->items, it.data(), it.size() * sizeof(FusedItem), hipMemcpyHostToDevice));
+    return FUGLBM_OK;
+}
+
+void drop_graph(fuglbm_sim *s) {
+    if (s->graph.exec) hipGraphExecDestroy(s->graph.exec);
+    s->graph = GraphCache{};
+}
+
+hipError_t launch_one_step(fuglbm_sim *s, int flip_parity, hipStream_t st) {
+    if (s->kernel == 2)
+        return launch_fused_d2q9(s->N, s->fp32, s->items, s->nitems, s->fsim, flip_parity, st);
+    return launch_step_generic(s->lattice, s->fp32, s->dc, s->ns, s->buf[flip_parity],
+                               s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
+                               s->status, st);
+}
+
+constexpr int GRAPH_STEPS = 32;  // even: a replay returns to the same parity
+
+fuglbm_status ensure_graph(fuglbm_sim *s) {
+    if (s->graph.exec && s->graph.kernel == s->kernel && s->graph.rows == s->rows)
+        return FUGLBM_OK;
+    drop_graph(s);
+    hipStream_t cs = capture_stream();
+    if (!cs) return fail(FUGLBM_EDEVICE, "cannot create capture stream");
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_STEPS; ++k) {
+        hipError_t e = launch_one_step(s, k & 1, cs);
+        if (e != hipSuccess) {
+            hipGraph_t g;
+            hipStreamEndCapture(cs, &g);
+            return hip_fail(e, "capture");
+        }
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    s->graph.exec = ex;
+    s->graph.steps = GRAPH_STEPS;
+    s->graph.kernel = s->kernel;
+    s->graph.rows = s->rows;
+    return FUGLBM_OK;
+}
+
+fuglbm_status sync_status(fuglbm_sim *s) {
+    HIP_TRY(hipStreamSynchronize(s->last_stream));
+    uint32_t st = 0;
+    HIP_TRY(hipMemcpy(&st, s->status, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    s->sticky |= st;
+    return FUGLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fuglbm_last_error(void) { return g_err.c_str(); }
+
+fuglbm_status fuglbm_init_mixture(const fuglbm_mixture_desc *d, fuglbm_mixture **out) {
+    if (!d || !out) return fail(FUGLBM_EINVAL, "null argument");
+    *out = nullptr;
+    const int N = d->ncomp;
+    if (N < 1 || N > FUGLBM_MAX_COMP) return fail(FUGLBM_EINVAL, "ncomp out of range");
+    if (!d->Tc_K || !d->pc_bar || !d->omega || !d->M_gmol)
+        return fail(FUGLBM_EINVAL, "null component array");
+    if (d->ref_comp < 0 || d->ref_comp >= N) return fail(FUGLBM_EINVAL, "ref_comp out of range");
+    if (!(d->T_K > 0) || !std::isfinite(d->T_K)) return fail(FUGLBM_EINVAL, "T_K must be > 0");
+    if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(FUGLBM_EINVAL, "tau must be > 1/2");
+    if (!(d->kappa_ref_lu >= 0) || !std::isfinite(d->kappa_ref_lu))
+        return fail(FUGLBM_EINVAL, "kappa_ref_lu must be >= 0");
+    for (int i = 0; i < N; ++i) {
+        if (!(d->Tc_K[i] > 0) || !(d->pc_bar[i] > 0) || !(d->M_gmol[i] > 0) ||
+            !std::isfinite(d->omega[i]) || !std::isfinite(d->Tc_K[i]) ||
+            !std::isfinite(d->pc_bar[i]) || !std::isfinite(d->M_gmol[i]))
+            return fail(FUGLBM_EINVAL, "component constants must be positive and finite");
+    }
+    if (d->kij) {
+        for (int i = 0; i < N; ++i) {
+            if (d->kij[i * N + i] != 0.0) return fail(FUGLBM_EINVAL, "kij diagonal must be 0");
+            for (int j = 0; j < N; ++j) {
+                if (!std::isfinite(d->kij[i * N + j]) || d->kij[i * N + j] != d->kij[j * N + i])
+                    return fail(FUGLBM_EINVAL, "kij must be finite and symmetric");
+                if (!(d->kij[i * N + j] < 1.0)) return fail(FUGLBM_EINVAL, "kij must be < 1");
+            }
+        }
+    }
+    auto *m = new (std::nothrow) fuglbm_mixture();
+    if (!m) return fail(FUGLBM_ENOMEM, "host allocation");
+    const double a_ref = d->a_ref_lu > 0 ? d->a_ref_lu : 2.0 / 49.0;
+    const double b_ref = d->b_ref_lu > 0 ? d->b_ref_lu : 2.0 / 21.0;
+    const double R = d->R_lu > 0 ? d->R_lu : 1.0;
+    const int c = d->ref_comp;
+    // reference component's critical point in lattice units from a and b
+    const double Tc_ref = (a_ref / b_ref) * (OMEGA_B / OMEGA_A) / R;
+    const double pc_ref = OMEGA_B * R * Tc_ref / b_ref;
+    const double Tsc = Tc_ref / d->Tc_K[c];     // lattice units per K
+    const double psc = pc_ref / d->pc_bar[c];   // lattice units per bar
+    m->N = N;
+    m->tau = d->tau;
+    m->RT = R * d->T_K * Tsc;
+    double a_lu[FUG_MAXC];
+    for (int i = 0; i < N; ++i) {
+        const double Tc = d->Tc_K[i] * Tsc, pc = d->pc_bar[i] * psc;
+        a_lu[i] = OMEGA_A * R * R * Tc * Tc / pc;
+        m->b[i] = OMEGA_B * R * Tc / pc;
+        const double w = d->omega[i];
+        const double mw = w <= 0.49 ? 0.374640 + 1.54226 * w - 0.26992 * w * w
+                                    : 0.379642 + 1.48503 * w - 0.164423 * w * w + 0.016666 * w * w * w;
+        const double sa = 1.0 + mw * (1.0 - std::sqrt(d->T_K / d->Tc_K[i]));
+        m->aa[i] = a_lu[i] * sa * sa;
+        m->M[i] = d->M_gmol[i] / d->M_gmol[c];
+    }
+    for (int i = 0; i < N; ++i) {
+        m->sqk[i] = std::sqrt(d->kappa_ref_lu * a_lu[i] / a_lu[c]);
+        for (int j = 0; j < N; ++j) {
+            const double k = d->kij ? d->kij[i * N + j] : 0.0;
+            m->aij[i * FUG_MAXC + j] = std::sqrt(m->aa[i] * m->aa[j]) * (1.0 - k);
+        }
+    }
+    *out = m;
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_lattice_constants(const fuglbm_mixture *m, double *out, size_t n) {
+    if (!m || !out) return fail(FUGLBM_EINVAL, "null argument");
+    const int N = m->N;
+    if (n < (size_t)(1 + 4 * N + N * N)) return fail(FUGLBM_EINVAL, "output too small");
+    size_t k = 0;
+    out[k++] = m->RT;
+    for (int i = 0; i < N; ++i) {
+        out[k++] = m->b[i];
+        out[k++] = m->aa[i];
+        out[k++] = m->sqk[i];
+        out[k++] = m->M[i];
+    }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) out[k++] = m->aij[i * FUG_MAXC + j];
+    return FUGLBM_OK;
+}
+
+void fuglbm_destroy_mixture(fuglbm_mixture *m) { delete m; }
+
+size_t fuglbm_fields_bytes(int32_t ncomp, fuglbm_lattice lattice, fuglbm_precision prec,
+                           int32_t nx, int32_t ny, int32_t nz) {
+    if (ncomp < 1 || ncomp > FUGLBM_MAX_COMP || nx < 1 || ny < 1 || nz < 1) return 0;
+    if (lattice != FUGLBM_D2Q9 && lattice != FUGLBM_D3Q19) return 0;
+    return carve(ncomp, lattice, prec == FUGLBM_FP32_STORAGE, nx, ny, nz).total;
+}
+
+fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice lattice,
+                                 fuglbm_precision prec, int32_t nx, int32_t ny, int32_t nz,
+                                 const double *rho, void *dev_buf, void *hip_stream,
+                                 fuglbm_sim **out) {
+    if (!mix || !rho || !out) return fail(FUGLBM_EINVAL, "null argument");
+    *out = nullptr;
+    if (lattice != FUGLBM_D2Q9 && lattice != FUGLBM_D3Q19) return fail(FUGLBM_EINVAL, "lattice");
+    if (prec != FUGLBM_FP64 && prec != FUGLBM_FP32_STORAGE) return fail(FUGLBM_EINVAL, "precision");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(FUGLBM_EINVAL, "grid sizes must be >= 1");
+    if (lattice == FUGLBM_D2Q9 && nz != 1) return fail(FUGLBM_EINVAL, "D2Q9 needs nz == 1");
+    const int64_t ns = (int64_t)nx * ny * nz;
+    if (ns > (int64_t)1 << 31) return fail(FUGLBM_EINVAL, "grid too large");
+    const int N = mix->N;
+    // physical admissibility of the initial field (rho_i > 0, finite, b_m rt < 1)
+    std::vector<double> rbar(N, 0.0);
+    for (int64_t s = 0; s < ns; ++s) {
+        double eta = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const double r = rho[(int64_t)i * ns + s];
+            if (!std::isfinite(r) || !(r > 0.0))
+                return fail(FUGLBM_EUNPHYSICAL, "rho_i must be finite and > 0");
+            eta += mix->b[i] * r / mix->M[i];
+            rbar[i] += r;
+        }
+        if (!(eta < 1.0)) return fail(FUGLBM_EUNPHYSICAL, "b_m * rt >= 1 (outside the EOS domain)");
+    }
+    auto *s = new (std::nothrow) fuglbm_sim();
+    if (!s) return fail(FUGLBM_ENOMEM, "host allocation");
+    s->mix = mix;
+    s->lattice = lattice;
+    s->fp32 = prec == FUGLBM_FP32_STORAGE;
+    s->nx = nx; s->ny = ny; s->nz = nz;
+    s->N = N;
+    s->Q = lattice_Q(lattice);
+    s->D = lattice_D(lattice);
+    s->ns = ns;
+    s->cv = carve(N, lattice, s->fp32, nx, ny, nz);
+    hipStream_t st = (hipStream_t)hip_stream;
+    s->last_stream = st;
+    if (dev_buf) {
+        if (((uintptr_t)dev_buf & 255) != 0) {
+            delete s;
+            return fail(FUGLBM_EINVAL, "dev_buf must be 256-byte aligned");
+        }
+        s->base = (char *)dev_buf;
+        s->owned = false;
+    } else {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, s->cv.total);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(FUGLBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        s->base = (char *)p;
+        s->owned = true;
+    }
+    s->buf[0] = s->base + s->cv.buf0;
+    s->buf[1] = s->base + s->cv.buf1;
+    s->dc = (SimConst *)(s->base + s->cv.cst);
+    s->status = (uint32_t *)(s->base + s->cv.status);
+    s->rho_f = (double *)(s->base + s->cv.rho);
+    s->psi_f = (double *)(s->base + s->cv.psi);
+    s->s_f = (double *)(s->base + s->cv.s);
+    s->j_f = (double *)(s->base + s->cv.j);
+    s->u_f = (double *)(s->base + s->cv.u);
+    s->snap = (double *)(s->base + s->cv.snap);
+    s->part = (double *)(s->base + s->cv.part);
+    s->fsim = (FusedSim *)(s->base + s->cv.fsim);
+    s->items = (FusedItem *)(s->base + s->cv.items);
+    s->parity = 0;
+    // constant block
+    SimConst &c = s->hc;
+    std::memset(&c, 0, sizeof(c));
+    c.N = N;
+    c.lattice = lattice;
+    c.nx = nx; c.ny = ny; c.nz = nz;
+    c.nsites = ns;
+    c.omega = 1.0 / mix->tau;
+    c.fcoef = 1.0 - 1.0 / (2.0 * mix->tau);
+    c.RT = mix->RT;
+    for (int i = 0; i < N; ++i) {
+        c.b[i] = mix->b[i];
+        c.M[i] = mix->M[i];
+        c.invM[i] = 1.0 / mix->M[i];
+        c.sqk[i] = mix->sqk[i];
+        c.rhobar[i] = s->fp32 ? rbar[i] / (double)ns : 0.0;
+        for (int j = 0; j < N; ++j) c.aij[i * FUG_MAXC + j] = mix->aij[i * FUG_MAXC + j];
+    }
+    fuglbm_status rc = FUGLBM_OK;
+    auto bail = [&](fuglbm_status r) {
+        if (s->owned) hipFree(s->base);
+        delete s;
+        return r;
+    };
+    hipError_t e = hipMemcpy(s->dc, &c, sizeof(SimConst), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(e, "upload constants"));
+    // stage rho in the second population buffer, then g = geq(rho, u = 0)
+    e = hipMemcpy(s->buf[1], rho, (size_t)N * ns * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(e, "upload rho"));
+    e = hipMemset(s->status, 0, 256);
+    if (e != hipSuccess) return bail(hip_fail(e, "clear status"));
+    e = launch_init(lattice, s->fp32, s->dc, ns, (const double *)s->buf[1], s->buf[0], st);
+    if (e != hipSuccess) return bail(hip_fail(e, "init kernel"));
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(hip_fail(e, "init sync"));
+    // fused-kernel tables (D2Q9)
+    FusedSim fs{};
+    fs.c = s->dc;
+    fs.buf[0] = s->buf[0];
+    fs.buf[1] = s->buf[1];
+    fs.status = s->status;
+    fs.parity = 0;
+    e = hipMemcpy(s->fsim, &fs, sizeof(FusedSim), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(e, "upload fused sim"));
+    s->kernel = lattice == FUGLBM_D2Q9 ? 2 : 1;
+    s->rows = lattice == FUGLBM_D2Q9 ? auto_rows(nx, ny) : 0;
+    if (lattice == FUGLBM_D2Q9) {
+        rc = build_items(s);
+        if (rc != FUGLBM_OK) return bail(rc);
+    }
+    s->step = 0;
+    s->snap_step = 0;
+    s->have_snap = false;
+    s->sticky = 0;
+    *out = s;
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
+    if (!s) return fail(FUGLBM_EINVAL, "null sim");
+    if (kernel < 0 || kernel > 2) return fail(FUGLBM_EINVAL, "kernel must be 0, 1 or 2");
+    if (kernel == 2 && s->lattice != FUGLBM_D2Q9)
+        return fail(FUGLBM_EINVAL, "the fused kernel is D2Q9 only");
+    if (rows < 0) return fail(FUGLBM_EINVAL, "rows must be >= 0");
+    const int k = kernel == 0 ? (s->lattice == FUGLBM_D2Q9 ? 2 : 1) : kernel;
+    int r = s->rows;
+    if (s->lattice == FUGLBM_D2Q9) {
+        r = rows == 0 ? auto_rows(s->nx, s->ny) : std::min<int>(rows, s->ny);
+        if (r < std::min(8, s->ny)) return fail(FUGLBM_EINVAL, "rows must be >= 8 (or the grid height)");
+    }
+    HIP_TRY(hipStreamSynchronize(s->last_stream));
+    s->kernel = k;
+    if (r != s->rows) {
+        s->rows = r;
+        fuglbm_status rc = build_items(s);
+        if (rc != FUGLBM_OK) return rc;
+    }
+    drop_graph(s);
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_sim_info(const fuglbm_sim *s, int32_t *Q, int32_t *D, int64_t *sites,
+                              int64_t *alg_bytes, int32_t *kernel) {
+    if (!s) return fail(FUGLBM_EINVAL, "null sim");
+    if (Q) *Q = s->Q;
+    if (D) *D = s->D;
+    if (sites) *sites = s->ns;
+    if (alg_bytes) *alg_bytes = 2 * (int64_t)s->Q * s->N * (s->fp32 ? 4 : 8) * s->ns;
+    if (kernel) *kernel = s->kernel;
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
+    if (!s) return fail(FUGLBM_EINVAL, "null sim");
+    if (nsteps < 0) return fail(FUGLBM_EINVAL, "nsteps must be >= 0");
+    if (s->sticky) return fail(FUGLBM_ENONFINITE, "simulation has a sticky device error");
+    hipStream_t st = (hipStream_t)hip_stream;
+    s->last_stream = st;
+    int64_t left = nsteps;
+    // odd parity first so that graph replays start from buffer 0
+    if (left > 0 && s->parity == 1 && left >= 2 * GRAPH_STEPS) {
+        hipError_t e = launch_one_step(s, s->parity, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        s->parity ^= 1;
+        --left;
+        ++s->step;
+    }
+    if (left >= 2 * GRAPH_STEPS && s->parity == 0) {
+        fuglbm_status rc = ensure_graph(s);
+        if (rc != FUGLBM_OK) return rc;
+        while (left >= GRAPH_STEPS) {
+            HIP_TRY(hipGraphLaunch(s->graph.exec, st));
+            left -= GRAPH_STEPS;
+            s->step += GRAPH_STEPS;
+        }
+    }
+    for (; left > 0; --left) {
+        hipError_t e = launch_one_step(s, s->parity, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        s->parity ^= 1;
+        ++s->step;
+    }
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_read_moments(fuglbm_sim *s, double *rho_out, double *u_out,
+                                  fuglbm_diag *diag) {
+    if (!s) return fail(FUGLBM_EINVAL, "null sim");
+    hipStream_t st = s->last_stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(launch_fields(s->lattice, s->fp32, s->dc, s->ns, s->buf[s->parity], s->rho_f,
+                          s->psi_f, s->s_f, s->j_f, u_out ? s->u_f : nullptr, s->status, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (rho_out)
+        HIP_TRY(hipMemcpy(rho_out, s->rho_f, (size_t)s->N * s->ns * 8, hipMemcpyDeviceToHost));
+    if (u_out)
+        HIP_TRY(hipMemcpy(u_out, s->u_f, (size_t)s->D * s->ns * 8, hipMemcpyDeviceToHost));
+    fuglbm_status rc = sync_status(s);
+    if (rc != FUGLBM_OK) return rc;
+    if (diag) {
+        rc = fuglbm_diagnostics(s, diag);
+        if (rc != FUGLBM_OK && rc != FUGLBM_ENONFINITE) return rc;
+    }
+    if (s->sticky) return fail(FUGLBM_ENONFINITE, "device status bits set");
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_diagnostics(fuglbm_sim *s, fuglbm_diag *diag) {
+    if (!s || !diag) return fail(FUGLBM_EINVAL, "null argument");
+    hipStream_t st = s->last_stream;
+    const int nblk = diag_blocks(s->ns);
+    const int N = s->N, nq = 2 * N + 3;
+    HIP_TRY(launch_diag(s->lattice, s->fp32, s->dc, s->ns, s->buf[s->parity], s->snap, s->part,
+                        nblk, s->have_snap ? 1 : 0, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<double> part((size_t)nblk * nq);
+    HIP_TRY(hipMemcpy(part.data(), s->part, part.size() * 8, hipMemcpyDeviceToHost));
+    std::vector<double> tot(nq, 0.0);
+    for (int b = 0; b < nblk; ++b)
+        for (int q = 0; q < nq; ++q) tot[q] += part[(size_t)b * nq + q];
+    std::memset(diag, 0, sizeof(*diag));
+    diag->step = s->step;
+    for (int i = 0; i < N; ++i) diag->mass[i] = tot[i];
+    for (int d = 0; d < 3; ++d) diag->momentum[d] = tot[2 * N + d];
+    double res = 0.0;
+    const int64_t K = s->step - s->snap_step;
+    if (s->have_snap && K > 0)
+        for (int i = 0; i < N; ++i) res = std::max(res, tot[N + i] / ((double)K * tot[i]));
+    diag->residual = res;
+    s->have_snap = true;
+    s->snap_step = s->step;
+    fuglbm_status rc = sync_status(s);
+    if (rc != FUGLBM_OK) return rc;
+    diag->status = s->sticky;
+    if (s->sticky) return fail(FUGLBM_ENONFINITE, "device status bits set");
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_read_populations(fuglbm_sim *s, double *g_out) {
+    if (!s || !g_out) return fail(FUGLBM_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(s->last_stream));
+    const size_t n = (size_t)s->N * s->Q * s->ns;
+    if (s->fp32) {
+        std::vector<float> tmp(n);
+        HIP_TRY(hipMemcpy(tmp.data(), s->buf[s->parity], n * 4, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < n; ++k) g_out[k] = (double)tmp[k];
+    } else {
+        HIP_TRY(hipMemcpy(g_out, s->buf[s->parity], n * 8, hipMemcpyDeviceToHost));
+    }
+    for (int i = 0; i < s->N; ++i)
+        for (int64_t t = 0; t < s->ns; ++t) g_out[(size_t)i * s->Q * s->ns + t] += s->hc.rhobar[i];
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_write_populations(fuglbm_sim *s, const double *g_in, int64_t step) {
+    if (!s || !g_in) return fail(FUGLBM_EINVAL, "null argument");
+    if (step < 0) return fail(FUGLBM_EINVAL, "step must be >= 0");
+    HIP_TRY(hipStreamSynchronize(s->last_stream));
+    const size_t n = (size_t)s->N * s->Q * s->ns;
+    if (s->fp32) {
+        std::vector<float> tmp(n);
+        for (size_t k = 0; k < n; ++k) tmp[k] = (float)g_in[k];
+        for (int i = 0; i < s->N; ++i)
+            for (int64_t t = 0; t < s->ns; ++t) {
+                const size_t k = (size_t)i * s->Q * s->ns + t;
+                tmp[k] = (float)(g_in[k] - s->hc.rhobar[i]);
+            }
+        HIP_TRY(hipMemcpy(s->buf[0], tmp.data(), n * 4, hipMemcpyHostToDevice));
+    } else {
+        HIP_TRY(hipMemcpy(s->buf[0], g_in, n * 8, hipMemcpyHostToDevice));
+    }
+    s->parity = 0;
+    s->step = step;
+    s->have_snap = false;
+    return FUGLBM_OK;
+}
+
+fuglbm_status fuglbm_poke_population(fuglbm_sim *s, int32_t comp, int32_t a, int64_t site,
+                                     double value) {
+    if (!s) return fail(FUGLBM_EINVAL, "null sim");
+    if (comp < 0 || comp >= s->N || a < 0 || a >= s->Q || site < 0 || site >= s->ns)
+        return fail(FUGLBM_EINVAL, "index out of range");
+    HIP_TRY(hipStreamSynchronize(s->last_stream));
+    const size_t k = ((size_t)comp * s->Q + a) * s->ns + site;
+    const double v = a == 0 ? value - s->hc.rhobar[comp] : value;
+    if (s->fp32) {
+        const float f = (float)v;
+        HIP_TRY(hipMemcpy((float *)s->buf[s->parity] + k, &f, 4, hipMemcpyHostToDevice));
+    } else {
+        HIP_TRY(hipMemcpy((double *)s->buf[s->parity] + k, &v, 8, hipMemcpyHostToDevice));
+    }
+    return FUGLBM_OK;
+}
+
+void fuglbm_destroy_sim(fuglbm_sim *s) {
+    if (!s) return;
+    hipStreamSynchronize(s->last_stream);
+    drop_graph(s);
+    if (s->owned) hipFree(s->base);
+    delete s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched stepping: D2Q9 simulations on the fused kernel that share the
+// component count and precision run as ONE launch per step over a combined
+// work-item table; the table is rebuilt only when the set of simulations
+// (or their buffer parities) changes.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchTable {
+    std::vector<fuglbm_sim *> sims;
+    std::vector<int> parity0;
+    FusedSim *dsims = nullptr;
+    FusedItem *ditems = nullptr;
+    size_t cap_sims = 0, cap_items = 0;
+    int nitems = 0;
+};
+
+std::map<std::pair<int, int>, BatchTable> &batch_tables() {
+    static std::map<std::pair<int, int>, BatchTable> t;
+    return t;
+}
+
+fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, hipStream_t st) {
+    HIP_TRY(hipStreamSynchronize(st));  // the old table may still be read by queued launches
+    std::vector<FusedSim> hs;
+    std::vector<FusedItem> logical;
+    for (size_t k = 0; k < group.size(); ++k) {
+        fuglbm_sim *s = group[k];
+        FusedSim fs{};
+        fs.c = s->dc;
+        fs.buf[0] = s->buf[0];
+        fs.buf[1] = s->buf[1];
+        fs.status = s->status;
+        fs.parity = s->parity;
+        hs.push_back(fs);
+        const int strips = (s->nx + FUSED_OUT - 1) / FUSED_OUT;
+        const int chunks = (s->ny + s->rows - 1) / s->rows;
+        for (int c = 0; c < chunks; ++c)
+            for (int t = 0; t < strips; ++t)
+                logical.push_back({(int32_t)k, t * FUSED_OUT, c * s->rows,
+                                   std::min(s->rows, s->ny - c * s->rows)});
+    }
+    const int n = (int)logical.size();
+    const int per = (n + 7) / 8;
+    std::vector<FusedItem> items((size_t)per * 8, FusedItem{-1, 0, 0, 0});
+    for (int b = 0; b < per * 8; ++b) {
+        const int li = (b % 8) * per + b / 8;
+        if (li < n) items[b] = logical[li];
+    }
+    if (hs.size() > bt.cap_sims) {
+        if (bt.dsims) hipFree(bt.dsims);
+        bt.cap_sims = hs.size() * 2;
+        HIP_TRY(hipMalloc(&bt.dsims, bt.cap_sims * sizeof(FusedSim)));
+    }
+    if (items.size() > bt.cap_items) {
+        if (bt.ditems) hipFree(bt.ditems);
+        bt.cap_items = items.size() * 2;
+        HIP_TRY(hipMalloc(&bt.ditems, bt.cap_items * sizeof(FusedItem)));
+    }
+    HIP_TRY(hipMemcpy(bt.dsims, hs.data(), hs.size() * sizeof(FusedSim), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bt.ditems, items.data(), items.size() * sizeof(FusedItem),
+                      hipMemcpyHostToDevice));
+    bt.nitems = (int)items.size();
+    bt.sims = group;
+    bt.parity0.clear();
+    for (auto *s : group) bt.parity0.push_back(s->parity);
+    return FUGLBM_OK;
+}
+
+}  // namespace
+
+extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count, int64_t nsteps,
+                                          void *hip_stream) {
+    if (count < 0 || (count > 0 && !sims)) return fail(FUGLBM_EINVAL, "bad sims array");
+    if (nsteps < 0) return fail(FUGLBM_EINVAL, "nsteps must be >= 0");
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::map<std::pair<int, int>, std::vector<fuglbm_sim *>> groups;
+    std::vector<fuglbm_sim *> others;
+    bool skipped = false;
+    for (int k = 0; k < count; ++k) {
+        fuglbm_sim *s = sims[k];
+        if (!s) return fail(FUGLBM_EINVAL, "null sim in batch");
+        for (int q = 0; q < k; ++q)
+            if (sims[q] == s) return fail(FUGLBM_EINVAL, "duplicate sim in batch");
+        if (s->sticky) {
+            skipped = true;
+            continue;
+        }
+        if (s->lattice == FUGLBM_D2Q9 && s->kernel == 2)
+            groups[{s->N, s->fp32 ? 1 : 0}].push_back(s);
+        else
+            others.push_back(s);
+    }
+    for (auto &kv : groups) {
+        auto &group = kv.second;
+        BatchTable &bt = batch_tables()[kv.first];
+        bool same = bt.sims == group;
+        int flip = 0;
+        if (same) {
+            flip = group[0]->parity ^ bt.parity0[0];
+            for (size_t k = 0; k < group.size(); ++k)
+                if ((group[k]->parity ^ bt.parity0[k]) != flip) same = false;
+        }
+        if (!same) {
+            fuglbm_status rc = build_batch(bt, group, st);
+            if (rc != FUGLBM_OK) return rc;
+            flip = 0;
+        }
+        for (int64_t k = 0; k < nsteps; ++k) {
+            hipError_t e = launch_fused_d2q9(kv.first.first, kv.first.second != 0, bt.ditems,
+                                             bt.nitems, bt.dsims, flip, st);
+            if (e != hipSuccess) return hip_fail(e, "batched step launch");
+            flip ^= 1;
+        }
+        for (auto *s : group) {
+            s->parity ^= (int)(nsteps & 1);
+            s->step += nsteps;
+            s->last_stream = st;
+        }
+    }
+    for (auto *s : others) {
+        fuglbm_status rc = fuglbm_step_n(s, nsteps, hip_stream);
+        if (rc != FUGLBM_OK) return rc;
+    }
+    if (skipped) return fail(FUGLBM_ENONFINITE, "some simulations have a sticky device error");
+    return FUGLBM_OK;
+}

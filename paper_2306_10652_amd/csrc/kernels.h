@@ -1,0 +1,40 @@
+// Kernel launchers (C++ linkage, internal to the library).
+#pragma once
+
+#include "lbm_common.h"
+
+// One work item of the fused D2Q9 kernel: a 60-column strip of a simulation
+// starting at column x0, output rows [y0, y0 + rows).  sim < 0: padding.
+struct FusedItem {
+    int32_t sim, x0, y0, rows;
+};
+
+// Per-simulation pointers for the fused kernel.  The source buffer of a
+// launch is buf[parity ^ flip], the destination the other one.
+struct FusedSim {
+    const SimConst *c;
+    void *buf[2];
+    uint32_t *status;
+    int32_t parity;
+    int32_t pad;
+};
+
+constexpr int FUSED_LANES = 64;
+constexpr int FUSED_OUT = 60;  // output columns per strip (2-column halo each side)
+
+hipError_t launch_init(int lattice, bool fp32, const SimConst *c, int64_t ns, const double *rho,
+                       void *g, hipStream_t st);
+hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int64_t ns,
+                               const void *gs, void *gd, double *rho_f, double *psi_f,
+                               double *s_f, double *j_f, uint32_t *status, hipStream_t st);
+hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
+                         double *rho_f, double *psi_f, double *s_f, double *j_f, double *u_f,
+                         uint32_t *status, hipStream_t st);
+hipError_t launch_diag(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
+                       double *snap, double *part, int nblk, int use_snap, hipStream_t st);
+int diag_blocks(int64_t ns);
+
+// Fused one-pass D2Q9 step over a table of work items (any mix of
+// simulations with the same component count and storage precision).
+hipError_t launch_fused_d2q9(int ncomp, bool fp32, const FusedItem *items, int nitems,
+                             const FusedSim *sims, int flip, hipStream_t st);

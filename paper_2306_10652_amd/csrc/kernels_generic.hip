@@ -1,0 +1,376 @@
+// Three-pass step for any lattice (D2Q9, D3Q19), FP64 or FP32 storage:
+//   pass 1  moments + local PR fugacity: rho_i, RT ln f_i, s = sum sqrt(kappa_j) rt_j, j
+//   pass 2  psi_i = RT ln f_i - sqrt(kappa_i) lap(s)             (Eq. (4)-(5))
+//   pass 3  F_i = -rt_i grad psi_i, G_i = grad rho_i, u, collide (Eq. (1)), push
+// One thread per site; fields between passes live in the simulation's
+// workspace.  Also: initial populations, the macroscopic read-out and the
+// per-block diagnostic partial sums.
+#include "kernels.h"
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <class L>
+__device__ __forceinline__ int64_t nb_site(int x, int y, int z, int a, int nx, int ny, int nz) {
+    int xx = x + L::ex(a), yy = y + L::ey(a), zz = z + L::ez(a);
+    xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+    return (int64_t)xx + (int64_t)nx * ((int64_t)yy + (int64_t)ny * zz);
+}
+
+// Lattice gradient in pairwise-difference form; phi(site) read through f.
+template <class L, class Fn>
+__device__ __forceinline__ void lattice_grad(const int64_t *nb, Fn f, double &gx, double &gy,
+                                             double &gz) {
+    gx = gy = gz = 0.0;
+#pragma unroll
+    for (int a = 1; a < L::Q; ++a) {
+        // visit each opposite pair once: the member with the first non-zero
+        // component positive
+        const int fx = L::ex(a), fy = L::ey(a), fz = L::ez(a);
+        const bool first = fx > 0 || (fx == 0 && (fy > 0 || (fy == 0 && fz > 0)));
+        if (!first) continue;
+        int o = 0;
+#pragma unroll
+        for (int b = 1; b < L::Q; ++b)
+            if (L::ex(b) == -fx && L::ey(b) == -fy && L::ez(b) == -fz) o = b;
+        const double d = f(nb[a]) - f(nb[o]);
+        const double wd = L::w(a) * d;
+        gx += fx * wd;
+        gy += fy * wd;
+        gz += fz * wd;
+    }
+    gx *= 3.0;
+    gy *= 3.0;
+    gz *= 3.0;
+}
+
+template <class L, typename ST>
+__global__ __launch_bounds__(TPB) void k_init(const SimConst *__restrict__ c,
+                                              const double *__restrict__ rho,
+                                              ST *__restrict__ g) {
+    const int64_t ns = c->nsites;
+    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (s >= ns) return;
+    const int N = c->N;
+    for (int i = 0; i < N; ++i) {
+        const double r = rho[(int64_t)i * ns + s];
+        st_pop(g + ((int64_t)i * L::Q) * ns + s, r - c->rhobar[i]);
+#pragma unroll
+        for (int a = 1; a < L::Q; ++a) st_pop(g + ((int64_t)i * L::Q + a) * ns + s, 0.0);
+    }
+}
+
+template <class L, typename ST>
+__global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict__ c,
+                                                     const ST *__restrict__ g,
+                                                     double *__restrict__ rho_f,
+                                                     double *__restrict__ psi_f,
+                                                     double *__restrict__ s_f,
+                                                     double *__restrict__ j_f,
+                                                     uint32_t *__restrict__ status) {
+    const int64_t ns = c->nsites;
+    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (s >= ns) return;
+    const int N = c->N;
+    double rt[FUG_MAXC];
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+    double rtt = 0.0, eta = 0.0, sv = 0.0;
+    uint32_t bad = 0;
+#pragma unroll
+    for (int i = 0; i < FUG_MAXC; ++i) {
+        rt[i] = 1.0;
+        if (i < N) {
+            double r = 0.0;
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                double v = ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
+                if (a == 0) v += c->rhobar[i];
+                r += v;
+                jx += L::ex(a) * v;
+                jy += L::ey(a) * v;
+                jz += L::ez(a) * v;
+            }
+            rho_f[(int64_t)i * ns + s] = r;
+            rt[i] = r * c->invM[i];
+            if (!(rt[i] > 0.0)) bad |= FUG_ST_NEGATIVE;
+            rtt += rt[i];
+            eta += c->b[i] * rt[i];
+            sv += c->sqk[i] * rt[i];
+        }
+    }
+    const double inv_rt = 1.0 / rtt;
+    double S[FUG_MAXC];
+    double am = 0.0;
+#pragma unroll
+    for (int i = 0; i < FUG_MAXC; ++i) {
+        S[i] = 0.0;
+        if (i < N) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < FUG_MAXC; ++j)
+                if (j < N) acc += rt[j] * c->aij[i * FUG_MAXC + j];
+            S[i] = acc * inv_rt;
+            am += rt[i] * inv_rt * S[i];
+        }
+    }
+    const double RT = c->RT;
+    const MixSums m = pr_mixture(rtt, eta, am, RT);
+    bad |= m.bad;
+#pragma unroll
+    for (int i = 0; i < FUG_MAXC; ++i) {
+        if (i < N) {
+            const double v = pr_RTlnf(m, RT, rt[i], c->b[i], S[i]);
+            if (!isfinite(v)) bad |= FUG_ST_NONFINITE;
+            psi_f[(int64_t)i * ns + s] = v;
+        }
+    }
+    s_f[s] = sv;
+    j_f[s] = jx;
+    j_f[ns + s] = jy;
+    if (L::D == 3) j_f[2 * ns + s] = jz;
+    if (bad) atomicOr(status, bad);
+}
+
+template <class L>
+__global__ __launch_bounds__(TPB) void k_interface(const SimConst *__restrict__ c,
+                                                   const double *__restrict__ s_f,
+                                                   double *__restrict__ psi_f) {
+    const int64_t ns = c->nsites;
+    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (s >= ns) return;
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((int64_t)nx * ny));
+    const double sc = s_f[s];
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 1; a < L::Q; ++a)
+        acc += L::w(a) * (s_f[nb_site<L>(x, y, z, a, nx, ny, nz)] - sc);
+    const double lap = 6.0 * acc;
+    const int N = c->N;
+    for (int i = 0; i < N; ++i) psi_f[(int64_t)i * ns + s] -= c->sqk[i] * lap;
+}
+
+// Force-corrected common velocity u = (j + F/2) / rho at one site.
+template <class L>
+__device__ __forceinline__ void site_velocity(const SimConst *c, int64_t s, const int64_t *nb,
+                                              const double *rho_f, const double *psi_f,
+                                              const double *j_f, double &ux, double &uy,
+                                              double &uz, double &rhot) {
+    const int64_t ns = c->nsites;
+    const int N = c->N;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    rhot = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double *ps = psi_f + (int64_t)i * ns;
+        double gx, gy, gz;
+        lattice_grad<L>(nb, [&](int64_t t) { return ps[t]; }, gx, gy, gz);
+        const double r = rho_f[(int64_t)i * ns + s];
+        const double rt = r * c->invM[i];
+        Fx -= rt * gx;
+        Fy -= rt * gy;
+        Fz -= rt * gz;
+        rhot += r;
+    }
+    ux = (j_f[s] + 0.5 * Fx) / rhot;
+    uy = (j_f[ns + s] + 0.5 * Fy) / rhot;
+    uz = (L::D == 3) ? (j_f[2 * ns + s] + 0.5 * Fz) / rhot : 0.0;
+}
+
+template <class L, typename ST>
+__global__ __launch_bounds__(TPB) void k_collide(const SimConst *__restrict__ c,
+                                                 const ST *__restrict__ gs, ST *__restrict__ gd,
+                                                 const double *__restrict__ rho_f,
+                                                 const double *__restrict__ psi_f,
+                                                 const double *__restrict__ j_f) {
+    const int64_t ns = c->nsites;
+    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (s >= ns) return;
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((int64_t)nx * ny));
+    int64_t nb[L::Q];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) nb[a] = nb_site<L>(x, y, z, a, nx, ny, nz);
+    double ux, uy, uz, rhot;
+    site_velocity<L>(c, s, nb, rho_f, psi_f, j_f, ux, uy, uz, rhot);
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const int N = c->N;
+    const double omega = c->omega, fcoef = c->fcoef;
+    for (int i = 0; i < N; ++i) {
+        const double *ps = psi_f + (int64_t)i * ns;
+        const double *rs = rho_f + (int64_t)i * ns;
+        double gx, gy, gz, Gx, Gy, Gz;
+        lattice_grad<L>(nb, [&](int64_t t) { return ps[t]; }, gx, gy, gz);
+        lattice_grad<L>(nb, [&](int64_t t) { return rs[t]; }, Gx, Gy, Gz);
+        const double r = rs[s];
+        const double rt = r * c->invM[i];
+        const double Fx = -rt * gx, Fy = -rt * gy, Fz = -rt * gz;
+        const double Fu = Fx * ux + Fy * uy + Fz * uz;
+        const double Gu = Gx * ux + Gy * uy + Gz * uz;
+        const double rb = c->rhobar[i];
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) {
+            double gv = ld_pop(gs + ((int64_t)i * L::Q + a) * ns + s);
+            if (a == 0) gv += rb;
+            double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
+                                      omega, fcoef);
+            if (a == 0) o -= rb;
+            st_pop(gd + ((int64_t)i * L::Q + a) * ns + nb[a], o);
+        }
+    }
+}
+
+template <class L>
+__global__ __launch_bounds__(TPB) void k_velocity(const SimConst *__restrict__ c,
+                                                  const double *__restrict__ rho_f,
+                                                  const double *__restrict__ psi_f,
+                                                  const double *__restrict__ j_f,
+                                                  double *__restrict__ u_f) {
+    const int64_t ns = c->nsites;
+    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (s >= ns) return;
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((int64_t)nx * ny));
+    int64_t nb[L::Q];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) nb[a] = nb_site<L>(x, y, z, a, nx, ny, nz);
+    double ux, uy, uz, rhot;
+    site_velocity<L>(c, s, nb, rho_f, psi_f, j_f, ux, uy, uz, rhot);
+    u_f[s] = ux;
+    u_f[ns + s] = uy;
+    if (L::D == 3) u_f[2 * ns + s] = uz;
+}
+
+// Diagnostics: per-block partial sums over a fixed site assignment
+// (block b, thread t handle sites t + TPB*(b + nblk*k)); the host adds the
+// block partials in block order, so the result is bitwise reproducible.
+// part[b][0..N) mass, [N..2N) sum |rho_i - snap_i|, [2N..2N+3) momentum.
+template <class L, typename ST>
+__global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
+                                              const ST *__restrict__ g,
+                                              double *__restrict__ snap,
+                                              double *__restrict__ part, int use_snap) {
+    __shared__ double red[TPB];
+    const int64_t ns = c->nsites;
+    const int N = c->N;
+    const int nq = 2 * N + 3;
+    const int64_t stride = (int64_t)gridDim.x * TPB;
+    for (int q = 0; q < nq; ++q) {
+        double acc = 0.0;
+        for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < ns; s += stride) {
+            if (q < 2 * N) {
+                const int i = q < N ? q : q - N;
+                double r = 0.0;
+#pragma unroll
+                for (int a = 0; a < L::Q; ++a) r += ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
+                r += c->rhobar[i];
+                if (q < N) {
+                    acc += r;
+                } else {
+                    if (use_snap) acc += fabs(r - snap[(int64_t)i * ns + s]);
+                    snap[(int64_t)i * ns + s] = r;
+                }
+            } else {
+                const int d = q - 2 * N;
+                for (int i = 0; i < N; ++i) {
+#pragma unroll
+                    for (int a = 1; a < L::Q; ++a) {
+                        const int e = d == 0 ? L::ex(a) : (d == 1 ? L::ey(a) : L::ez(a));
+                        if (e != 0) acc += e * ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
+                    }
+                }
+            }
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = TPB / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nq + q] = red[0];
+        __syncthreads();
+    }
+}
+
+inline unsigned nblocks(int64_t ns) { return (unsigned)((ns + TPB - 1) / TPB); }
+
+template <class L, typename ST>
+hipError_t step_generic_t(const SimConst *c, int64_t ns, const void *gs, void *gd, double *rho_f,
+                          double *psi_f, double *s_f, double *j_f, uint32_t *status,
+                          hipStream_t st) {
+    const unsigned nb = nblocks(ns);
+    hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, (const ST *)gs,
+                       rho_f, psi_f, s_f, j_f, status);
+    hipLaunchKernelGGL((k_interface<L>), dim3(nb), dim3(TPB), 0, st, c, s_f, psi_f);
+    hipLaunchKernelGGL((k_collide<L, ST>), dim3(nb), dim3(TPB), 0, st, c, (const ST *)gs,
+                       (ST *)gd, rho_f, psi_f, j_f);
+    return hipGetLastError();
+}
+
+template <class L, typename ST>
+hipError_t fields_generic_t(const SimConst *c, int64_t ns, const void *g, double *rho_f,
+                            double *psi_f, double *s_f, double *j_f, double *u_f,
+                            uint32_t *status, hipStream_t st) {
+    const unsigned nb = nblocks(ns);
+    hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, (const ST *)g,
+                       rho_f, psi_f, s_f, j_f, status);
+    hipLaunchKernelGGL((k_interface<L>), dim3(nb), dim3(TPB), 0, st, c, s_f, psi_f);
+    if (u_f)
+        hipLaunchKernelGGL((k_velocity<L>), dim3(nb), dim3(TPB), 0, st, c, rho_f, psi_f, j_f,
+                           u_f);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init(int lattice, bool fp32, const SimConst *c, int64_t ns, const double *rho,
+                       void *g, hipStream_t st) {
+    const unsigned nb = nblocks(ns);
+    if (lattice == 0) {
+        if (fp32) hipLaunchKernelGGL((k_init<D2Q9, float>), dim3(nb), dim3(TPB), 0, st, c, rho, (float *)g);
+        else hipLaunchKernelGGL((k_init<D2Q9, double>), dim3(nb), dim3(TPB), 0, st, c, rho, (double *)g);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_init<D3Q19, float>), dim3(nb), dim3(TPB), 0, st, c, rho, (float *)g);
+        else hipLaunchKernelGGL((k_init<D3Q19, double>), dim3(nb), dim3(TPB), 0, st, c, rho, (double *)g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int64_t ns,
+                               const void *gs, void *gd, double *rho_f, double *psi_f,
+                               double *s_f, double *j_f, uint32_t *status, hipStream_t st) {
+    if (lattice == 0)
+        return fp32 ? step_generic_t<D2Q9, float>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st)
+                    : step_generic_t<D2Q9, double>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st);
+    return fp32 ? step_generic_t<D3Q19, float>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st)
+                : step_generic_t<D3Q19, double>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st);
+}
+
+hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
+                         double *rho_f, double *psi_f, double *s_f, double *j_f, double *u_f,
+                         uint32_t *status, hipStream_t st) {
+    if (lattice == 0)
+        return fp32 ? fields_generic_t<D2Q9, float>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st)
+                    : fields_generic_t<D2Q9, double>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st);
+    return fp32 ? fields_generic_t<D3Q19, float>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st)
+                : fields_generic_t<D3Q19, double>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st);
+}
+
+hipError_t launch_diag(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
+                       double *snap, double *part, int nblk, int use_snap, hipStream_t st) {
+    if (lattice == 0) {
+        if (fp32) hipLaunchKernelGGL((k_diag<D2Q9, float>), dim3(nblk), dim3(TPB), 0, st, c, (const float *)g, snap, part, use_snap);
+        else hipLaunchKernelGGL((k_diag<D2Q9, double>), dim3(nblk), dim3(TPB), 0, st, c, (const double *)g, snap, part, use_snap);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_diag<D3Q19, float>), dim3(nblk), dim3(TPB), 0, st, c, (const float *)g, snap, part, use_snap);
+        else hipLaunchKernelGGL((k_diag<D3Q19, double>), dim3(nblk), dim3(TPB), 0, st, c, (const double *)g, snap, part, use_snap);
+    }
+    return hipGetLastError();
+}
+
+int diag_blocks(int64_t ns) {
+    const int64_t b = (ns + TPB - 1) / TPB;
+    return (int)(b < 1024 ? b : 1024);
+}

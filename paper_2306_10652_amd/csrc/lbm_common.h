@@ -1,0 +1,149 @@
+// Device-side definitions shared by the gfx950 kernels and the host library:
+// per-simulation constant block, lattice velocity sets, the local
+// Peng-Robinson fugacity and the per-(component, direction) collision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FUG_MAXC 16
+
+// Status bits (mirrors FUGLBM_ST_* of the public header).
+#define FUG_ST_NONFINITE 1u
+#define FUG_ST_COVOLUME 2u
+#define FUG_ST_NEGATIVE 4u
+
+// Constants of one simulation, lattice units, FP64.  Lives in device memory
+// (one per simulation) and is read with wave-uniform loads.
+struct SimConst {
+    int32_t N;            // components
+    int32_t lattice;      // 0 D2Q9, 1 D3Q19
+    int32_t nx, ny, nz;
+    int32_t pad0;
+    int64_t nsites;
+    double omega;         // 1 / tau
+    double fcoef;         // 1 - 1 / (2 tau)
+    double RT;
+    double b[FUG_MAXC];
+    double M[FUG_MAXC];
+    double invM[FUG_MAXC];
+    double sqk[FUG_MAXC];     // sqrt(kappa_i)
+    double rhobar[FUG_MAXC];  // FP32-storage offset of the rest population
+    double aij[FUG_MAXC * FUG_MAXC];  // (a alpha)_ij, row-major, stride FUG_MAXC
+};
+
+// ---------------------------------------------------------------------------
+// Velocity sets.  D2Q9 order: rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-).
+// D3Q19 order: rest, 6 faces, 12 edges; opposite pairs at (a, a+1) for a odd.
+// ---------------------------------------------------------------------------
+struct D2Q9 {
+    static constexpr int Q = 9;
+    static constexpr int D = 2;
+    __host__ __device__ static constexpr int ex(int a) {
+        return a == 1 || a == 5 || a == 8 ? 1 : (a == 3 || a == 6 || a == 7 ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ey(int a) {
+        return a == 2 || a == 5 || a == 6 ? 1 : (a == 4 || a == 7 || a == 8 ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ez(int) { return 0; }
+    __host__ __device__ static constexpr double w(int a) {
+        return a == 0 ? 4.0 / 9.0 : (a <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+};
+
+struct D3Q19 {
+    static constexpr int Q = 19;
+    static constexpr int D = 3;
+    // faces: 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z
+    // edges: 7 (+x+y) 8 (-x-y) 9 (+x-y) 10 (-x+y) 11 (+x+z) 12 (-x-z)
+    //        13 (+x-z) 14 (-x+z) 15 (+y+z) 16 (-y-z) 17 (+y-z) 18 (-y+z)
+    __host__ __device__ static constexpr int ex(int a) {
+        return (a == 1 || a == 7 || a == 9 || a == 11 || a == 13) ? 1
+             : ((a == 2 || a == 8 || a == 10 || a == 12 || a == 14) ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ey(int a) {
+        return (a == 3 || a == 7 || a == 10 || a == 15 || a == 17) ? 1
+             : ((a == 4 || a == 8 || a == 9 || a == 16 || a == 18) ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ez(int a) {
+        return (a == 5 || a == 11 || a == 14 || a == 15 || a == 18) ? 1
+             : ((a == 6 || a == 12 || a == 13 || a == 16 || a == 17) ? -1 : 0);
+    }
+    __host__ __device__ static constexpr double w(int a) {
+        return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Peng-Robinson ln f_i for one component, given mixture sums at a site.
+//   eta = b_m rt = sum_j b_j rt_j,  am = sum_ij x_i x_j (a alpha)_ij,
+//   Si  = sum_j x_j (a alpha)_ij.
+// Returns RT ln f_i in the combined-logarithm form (defined for p <= 0):
+//   RT ln(rt_i RT/(1-eta)) + RT (b_i/b_m)(Z-1)
+//     - Lambda/(2 sqrt2 b_m) (2 S_i - a_m b_i / b_m),
+//   Lambda = ln[(1 + (1+sqrt2) eta) / (1 + (1-sqrt2) eta)].
+// The terms shared by all components are passed in precomputed.
+// ---------------------------------------------------------------------------
+struct MixSums {
+    double rt;         // total molar density
+    double inv_bm;     // 1 / b_m
+    double zm1;        // Z - 1
+    double lam_c;      // Lambda / (2 sqrt2 b_m)
+    double am;
+    double log_pref;   // ln(RT / (1 - eta))
+    uint32_t bad;      // status bits
+};
+
+__device__ __forceinline__ MixSums pr_mixture(double rt, double eta, double am, double RT) {
+    MixSums m;
+    m.rt = rt;
+    m.am = am;
+    const double one_m_eta = 1.0 - eta;
+    m.bad = (one_m_eta > 0.0) ? 0u : FUG_ST_COVOLUME;
+    const double bm = eta / rt;
+    m.inv_bm = 1.0 / bm;
+    const double den = 1.0 + 2.0 * eta - eta * eta;
+    // Z - 1 = p / (rt RT) - 1,  p = rt RT/(1 - eta) - am rt^2 / den
+    m.zm1 = eta / one_m_eta - am * rt / (RT * den);
+    const double s2 = 1.4142135623730951;
+    const double lam = log((1.0 + (1.0 + s2) * eta) / (1.0 + (1.0 - s2) * eta));
+    m.lam_c = lam * m.inv_bm * (0.5 / s2);
+    m.log_pref = log(RT / one_m_eta);
+    return m;
+}
+
+__device__ __forceinline__ double pr_RTlnf(const MixSums &m, double RT, double rt_i,
+                                           double b_i, double S_i) {
+    const double bi_bm = b_i * m.inv_bm;
+    return RT * (log(rt_i) + m.log_pref + bi_bm * m.zm1)
+         - m.lam_c * (2.0 * S_i - m.am * bi_bm);
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one (component, direction): Eq. (1a) with geq of Eq. (1b)
+// (rho^c = 0) and the forcing term of Eq. (1c); cs^2 = 1/3.
+// ---------------------------------------------------------------------------
+template <class L>
+__device__ __forceinline__ double collide_one(int a, double g, double rho, double ux,
+                                              double uy, double uz, double Fx, double Fy,
+                                              double Fz, double Gx, double Gy, double Gz,
+                                              double uu, double Fu, double Gu, double omega,
+                                              double fcoef) {
+    const double exa = L::ex(a), eya = L::ey(a), eza = L::ez(a);
+    const double eu = exa * ux + eya * uy + eza * uz;
+    const double eF = exa * Fx + eya * Fy + eza * Fz;
+    const double eG = exa * Gx + eya * Gy + eza * Gz;
+    const double e2 = exa * exa + eya * eya + eza * eza;
+    const double wa = L::w(a);
+    const double sq = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
+    const double geq = (a == 0) ? rho + wa * rho * sq : wa * rho * sq;
+    const double Fa = wa * (3.0 * (eF - Fu) + 9.0 * eu * eF)
+                    + wa * (-Gu + 3.0 * eu * eG + 0.5 * (3.0 * e2 - (double)L::D) * Gu);
+    return g - omega * (g - geq) + fcoef * Fa;
+}
+
+// Storage conversion (FP64 or FP32 deviation storage).
+__device__ __forceinline__ double ld_pop(const double *p) { return *p; }
+__device__ __forceinline__ double ld_pop(const float *p) { return (double)*p; }
+__device__ __forceinline__ void st_pop(double *p, double v) { *p = v; }
+__device__ __forceinline__ void st_pop(float *p, double v) { *p = (float)v; }

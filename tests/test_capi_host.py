@@ -1,0 +1,81 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+``include/fuglbm.h`` declares, and its host-only logic (lattice-unit
+constants, argument validation, buffer sizes) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from inputs import components as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fuglbm.h")
+
+
+def _capi():
+    from paper_2306_10652_amd import capi
+    if not os.path.exists(capi.LIB_PATH):
+        from paper_2306_10652_amd.build import build_library
+        build_library(verbose=False)
+    return capi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fuglbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_library_export_the_same_functions():
+    capi = _capi()
+    L = capi.lib()
+    names = declared_functions()
+    assert names == sorted(capi.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("comps,T,kij_seed", [
+    (C.DROPLET_3, 250.0, None),
+    (C.N_ALKANES, 325.0, 4),
+    ([C.TABLE_I["C1"]], 177.24, None),
+])
+def test_lattice_constants_match_oracle_units(comps, T, kij_seed):
+    """The library's own unit conversion (Section III.A anchors, Eq. (6)-(8)
+    kappa, alpha(T)) reproduces the oracle's, independently written."""
+    capi = _capi()
+    from inputs.fields import draw_kij
+    from oracle.lbm import oracle_mixture
+    kij = None if kij_seed is None else draw_kij(len(comps), 0.0, 0.05, kij_seed)
+    mix = capi.Mixture.from_components(comps, T, kij, kappa_ref=0.03, tau=0.8)
+    om = oracle_mixture(comps, T, kij, kappa_ref=0.03, tau=0.8)
+    np.testing.assert_allclose(mix.lattice_constants(), om.lattice_constants(), rtol=1e-13,
+                               atol=0)
+
+
+def test_mixture_argument_validation():
+    capi = _capi()
+    c = C.DROPLET_3
+    with pytest.raises(capi.FuglbmError) as e:
+        capi.Mixture.from_components(c, 250.0, tau=0.5)
+    assert e.value.status == 1
+    bad = np.zeros((3, 3))
+    bad[0, 1] = 0.1
+    with pytest.raises(capi.FuglbmError):
+        capi.Mixture.from_components(c, 250.0, bad)          # asymmetric
+    with pytest.raises(capi.FuglbmError):
+        capi.Mixture.from_components(c, -1.0)
+    with pytest.raises(capi.FuglbmError):
+        capi.Mixture([1.0] * 17, [1.0] * 17, [0.0] * 17, [1.0] * 17, 300.0)
+
+
+def test_fields_bytes():
+    capi = _capi()
+    L = capi.lib()
+    b64 = L.fuglbm_fields_bytes(10, capi.D2Q9, capi.FP64, 1024, 1024, 1)
+    b32 = L.fuglbm_fields_bytes(10, capi.D2Q9, capi.FP32_STORAGE, 1024, 1024, 1)
+    pop64 = 2 * 9 * 10 * 8 * 1024 * 1024
+    assert b64 >= pop64 and b64 - b32 == pop64 // 2
+    assert L.fuglbm_fields_bytes(0, 0, 0, 8, 8, 1) == 0
+    assert L.fuglbm_fields_bytes(3, 1, 0, 8, 8, 8) >= 2 * 19 * 3 * 8 * 512

@@ -1,0 +1,139 @@
+"""System behaviour of the GPU library through the C ABI: exact mass
+conservation, the uniform fixed point, bitwise determinism, batched ==
+single, full coverage of the push-streaming writes (NaN canary),
+checkpoint/resume, sticky device errors and their isolation in a batch."""
+import numpy as np
+import pytest
+
+from tests import workloads as W
+from tests.test_gpu_parity import _capi, report
+
+pytestmark = pytest.mark.gpu
+
+
+def make(wl, precision=0, capi=None):
+    capi = capi or _capi()
+    mix = wl.gpu_mixture()
+    sim = capi.Simulation(mix, wl.lattice, precision, wl.shape, wl.rho)
+    sim._mix = mix
+    return sim
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mass_conservation(precision):
+    wl = W.droplet64()
+    sim = make(wl, precision)
+    d0 = sim.diagnostics()
+    sim.step_n(500)
+    d1 = sim.diagnostics()
+    drift = np.max(np.abs(d1["mass"] - d0["mass"]) / d0["mass"])
+    report("mass", precision=precision, drift=drift, residual=d1["residual"])
+    assert d1["status"] == 0
+    assert drift <= (1e-13 if precision == 0 else 1e-6)
+
+
+def test_uniform_state_bitwise_fixed_point():
+    from inputs import fields as Fi
+    for lattice, shape in ((0, (70, 9)), (1, (9, 8, 7))):
+        wl = W.random_droplet(3, shape, seed=3, lattice=lattice)
+        rho = Fi.uniform(shape[0], shape[1], [1.1, 0.4, 0.2], nz=shape[2] if lattice else 1)
+        wl.rho = rho
+        sim = make(wl)
+        g0 = sim.read_populations()
+        sim.step_n(5)
+        assert np.array_equal(sim.read_populations(), g0)
+
+
+def test_bitwise_determinism_and_batched_equals_single():
+    capi = _capi()
+    wls = [W.droplet64(seed=s) for s in (1, 2, 3)]
+    singles = []
+    for wl in wls:
+        s = make(wl, capi=capi)
+        s.step_n(100)
+        singles.append(s.read_populations())
+    again = make(wls[0], capi=capi)
+    again.step_n(100)
+    assert np.array_equal(again.read_populations(), singles[0])
+    batch = [make(wl, capi=capi) for wl in wls]
+    capi.step_many(batch, 37)
+    capi.step_many(batch, 63)
+    for s, ref in zip(batch, singles):
+        assert np.array_equal(s.read_populations(), ref)
+
+
+def test_fused_and_generic_kernels_agree():
+    wl = W.random_droplet(5, (93, 40), seed=9)
+    a = make(wl)
+    b = make(wl)
+    b.set_tuning(1, 0)
+    a.step_n(50)
+    b.step_n(50)
+    ra, rb = a.read_moments()["rho"], b.read_moments()["rho"]
+    assert np.max(np.abs(ra - rb) / rb) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_destination_written_nan_canary(precision):
+    """Fill the destination buffer with NaN, take one step: every population
+    of the new state must be finite (push streaming writes each slot once)."""
+    import torch
+    wl = W.random_droplet(4, (67, 33), seed=4)
+    sim = make(wl, precision)
+    Q, ns = 9, 67 * 33
+    pop_bytes = 4 * Q * ns * (4 if precision else 8)
+    pop_bytes = (pop_bytes + 255) // 256 * 256
+    base = (sim._buf.data_ptr() + 255) & ~255
+    off = base - sim._buf.data_ptr() + pop_bytes
+    view = sim._buf[off:off + pop_bytes]
+    fl = view.view(torch.float32 if precision else torch.float64)
+    fl.fill_(float("nan"))
+    torch.cuda.synchronize()
+    sim.step_n(1)
+    g = sim.read_populations()
+    assert np.all(np.isfinite(g))
+
+
+def test_checkpoint_resume_bitwise():
+    wl = W.droplet64()
+    a = make(wl)
+    a.step_n(120)
+    ref = a.read_populations()
+    b = make(wl)
+    b.step_n(60)
+    ck = b.read_populations()
+    c = make(wl)
+    c.write_populations(ck, 60)
+    c.step_n(60)
+    assert np.array_equal(c.read_populations(), ref)
+
+
+def test_unphysical_input_rejected():
+    capi = _capi()
+    wl = W.droplet64()
+    bad = wl.rho.copy()
+    bad[1, 0, 3, 4] = -1.0
+    mix = wl.gpu_mixture()
+    with pytest.raises(capi.FuglbmError) as e:
+        capi.Simulation(mix, 0, 0, wl.shape, bad)
+    assert e.value.status == 4
+
+
+def test_sticky_error_and_isolation_in_batch():
+    capi = _capi()
+    wls = [W.droplet64(seed=s) for s in (1, 2)]
+    good_ref = make(wls[1], capi=capi)
+    good_ref.step_n(20)
+    ref = good_ref.read_populations()
+    a, b = make(wls[0], capi=capi), make(wls[1], capi=capi)
+    a.poke(0, 0, 64 * 32 + 32, float("nan"))
+    rc = capi.fuglbm_step_many([a, b], 10)
+    assert rc == 0
+    d = a.diagnostics()
+    assert d["rc"] == 5 and d["status"] & 1
+    with pytest.raises(capi.FuglbmError) as e:
+        a.step_n(1)
+    assert e.value.status == 5
+    rc = capi.fuglbm_step_many([a, b], 10)
+    assert rc == 5                      # a skipped, b advanced
+    assert np.array_equal(b.read_populations(), ref)

@@ -1,0 +1,86 @@
+"""Seeded workloads for the tests: the same physical description feeds the
+GPU library (through ``capi.Mixture``) and the CPU oracle (through
+``oracle.lbm.oracle_mixture``); initial fields come from ``inputs``."""
+import numpy as np
+
+from inputs import components as C
+from inputs import fields as Fi
+
+_STATES = None
+
+
+def states():
+    global _STATES
+    if _STATES is None:
+        _STATES = Fi.load_phase_states()
+    return _STATES
+
+
+class Workload:
+    def __init__(self, comps, T, rho, shape, kij=None, kappa_ref=0.02, tau=1.0, lattice=0):
+        self.comps, self.T, self.rho, self.shape = list(comps), T, rho, tuple(shape)
+        self.kij, self.kappa_ref, self.tau, self.lattice = kij, kappa_ref, tau, lattice
+
+    @property
+    def N(self):
+        return len(self.comps)
+
+    def gpu_mixture(self):
+        from paper_2306_10652_amd.capi import Mixture
+        return Mixture.from_components(self.comps, self.T, self.kij,
+                                       kappa_ref=self.kappa_ref, tau=self.tau)
+
+    def oracle(self):
+        from oracle.lbm import OracleLBM, oracle_mixture
+        m = oracle_mixture(self.comps, self.T, self.kij, kappa_ref=self.kappa_ref, tau=self.tau)
+        return OracleLBM(m, self.lattice, self.shape, self.rho)
+
+
+def droplet64(noise=1e-3, seed=1, n=64, R=16.0):
+    """64 x 64 droplet of C1/C3/nC5 at 250 K (flash at 50 bar)."""
+    st = states()["droplet3"]
+    rho = Fi.droplet(n, n, st["rho_L"], st["rho_V"], R)
+    if noise:
+        rho = Fi.add_noise(rho, noise, seed)
+    return Workload(C.DROPLET_3, 250.0, rho, (n, n))
+
+
+def vle(case, nx=256, ny=32, S_V=0.5):
+    """Flat-interface slab of Table II case `case` (C1..C6), liquid in the middle half."""
+    st = states()["vle%d" % case]
+    comps, T, _ = C.table_ii_components(case)
+    rho = Fi.slab(nx, ny, st["rho_V"], st["rho_L"], S_V)
+    return Workload(comps, T, rho, (nx, ny))
+
+
+def spinodal10(n=1024, noise=1e-2, seed=4):
+    """Ten-component n-alkane mixture, uniform lever-rule density +-1 % noise."""
+    st = states()["spinodal10"]
+    rho = Fi.add_noise(Fi.uniform(n, n, st["rho_uniform"]), noise, seed)
+    return Workload(C.N_ALKANES, 325.0, rho, (n, n), kij=np.array(st["kij"]))
+
+
+def random_droplet(N, shape, seed, lattice=0, noise=1e-2):
+    """Small ragged-grid droplet/sphere of the first N n-alkanes (N <= 10) or
+    of C1 pseudo-components (N > 10); used for edge-case parity."""
+    rng = np.random.default_rng(seed)
+    if N <= 10:
+        comps = C.N_ALKANES[:N]
+    else:
+        comps = [C.N_ALKANES[k % 10] for k in range(N)]
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if len(shape) > 2 else 1
+    # liquid-like and vapour-like molar densities at eta = 0.55 / 0.05
+    from oracle.lbm import oracle_mixture   # constants only (b_i), test side
+    m = oracle_mixture(comps, 300.0)
+    x = rng.dirichlet(np.ones(N))
+    rtL = x * 0.55 / (x @ m.pr.b)
+    rtV = x * 0.05 / (x @ m.pr.b)
+    rho_L, rho_V = rtL * m.M, rtV * m.M
+    R = 0.3 * min(nx, ny)
+    z, y, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((xx - nx / 2) ** 2 + (y - ny / 2) ** 2 + ((z - nz / 2) ** 2 if nz > 1 else 0))
+    t = np.tanh(2 * (r - R) / 4.0)
+    rho = (0.5 * (rho_L + rho_V))[:, None, None, None] - (0.5 * (rho_L - rho_V))[:, None, None, None] * t
+    rho = Fi.add_noise(rho, noise, seed)
+    return Workload(comps, 300.0, rho, (nx, ny, nz) if lattice else (nx, ny), lattice=lattice)
