@@ -123,7 +123,22 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
+                    help="restrict the GPU legs (profiling runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB, 5 times "
+                         "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
+    if args.calib_copy_mib:
+        import torch
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(calib_copy_bytes=n * 4, launches=5)))
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported "
               "(multi-GPU sharding is design-only)" % args.gpus, file=sys.stderr)
@@ -132,6 +147,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.precision != "both":
+        r = time_gpu(0 if args.precision == "fp64" else 1, args.steps, args.warmup, args.n)
+        print(json.dumps(dict(precision=args.precision, **{k: v for k, v in r.items()
+                                                             if k != "mass"})), flush=True)
+        return
     r64 = time_gpu(0, args.steps, args.warmup, args.n)
     r32 = time_gpu(1, args.steps, args.warmup, args.n)
     traffic = pmc_traffic(r64["alg_bytes"])

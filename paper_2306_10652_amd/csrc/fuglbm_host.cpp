@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -41,13 +42,40 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int lattice_Q(int lat) { return lat == 0 ? 9 : 19; }
 int lattice_D(int lat) { return lat == 0 ? 2 : 3; }
 
-// Fused-kernel rows per work item: enough items to fill 256 CUs a few
-// times, rows >= 8, at most the grid height.
-int auto_rows(int nx, int ny) {
+// Fused-kernel rows per work item.  A work item re-reads 4 warm-up rows, so
+// longer items waste less; items run in rounds of (CUs x resident
+// workgroups per CU).  Pick rows (>= 8, <= ny) minimising
+// rounds * (rows + 4).
+int compute_units() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+int auto_rows(int nx, int ny, int ncomp, bool fp32) {
     const int strips = (nx + FUSED_OUT - 1) / FUSED_OUT;
-    int rows = 64;
-    while (rows > 8 && (int64_t)strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
-    return std::min(rows, ny);
+    const int64_t slots = (int64_t)compute_units() * fused_blocks_per_cu(ncomp, fp32);
+    if (ny <= 8) return ny;
+    int best = 8;
+    int64_t best_cost = INT64_MAX;
+    for (int rows = 8; rows <= ny; ++rows) {
+        const int64_t items = (int64_t)strips * ((ny + rows - 1) / rows);
+        const int64_t rounds = (items + slots - 1) / slots;
+        const int64_t cost = rounds * (rows + 4);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = rows;
+        }
+    }
+    return best;
 }
 
 }  // namespace
@@ -429,7 +457,7 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     e = hipMemcpy(s->fsim, &fs, sizeof(FusedSim), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(e, "upload fused sim"));
     s->kernel = lattice == FUGLBM_D2Q9 ? 2 : 1;
-    s->rows = lattice == FUGLBM_D2Q9 ? auto_rows(nx, ny) : 0;
+    s->rows = lattice == FUGLBM_D2Q9 ? auto_rows(nx, ny, N, s->fp32) : 0;
     if (lattice == FUGLBM_D2Q9) {
         rc = build_items(s);
         if (rc != FUGLBM_OK) return bail(rc);
@@ -451,7 +479,7 @@ fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     const int k = kernel == 0 ? (s->lattice == FUGLBM_D2Q9 ? 2 : 1) : kernel;
     int r = s->rows;
     if (s->lattice == FUGLBM_D2Q9) {
-        r = rows == 0 ? auto_rows(s->nx, s->ny) : std::min<int>(rows, s->ny);
+        r = rows == 0 ? auto_rows(s->nx, s->ny, s->N, s->fp32) : std::min<int>(rows, s->ny);
         if (r < std::min(8, s->ny)) return fail(FUGLBM_EINVAL, "rows must be >= 8 (or the grid height)");
     }
     HIP_TRY(hipStreamSynchronize(s->last_stream));

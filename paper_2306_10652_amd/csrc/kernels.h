@@ -36,5 +36,8 @@ int diag_blocks(int64_t ns);
 
 // Fused one-pass D2Q9 step over a table of work items (any mix of
 // simulations with the same component count and storage precision).
+// Resident workgroups of the fused kernel per CU (occupancy query).
+int fused_blocks_per_cu(int ncomp, bool fp32);
+
 hipError_t launch_fused_d2q9(int ncomp, bool fp32, const FusedItem *items, int nitems,
                              const FusedSim *sims, int flip, hipStream_t st);

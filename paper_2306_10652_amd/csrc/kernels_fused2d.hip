@@ -6,20 +6,17 @@
 // workgroup has one wavefront per component (lane = column): a lane keeps
 // only its own component's 9 populations of the rows in flight, in
 // registers.  Sums over components go through LDS.  Per lead row r (output
-// row y = r - 2), with three workgroup barriers:
+// row y = r - 2), with two workgroup barriers:
 //
-//   A  (all)  moments of row r -> LDS: rt_i, j_i
-//   B  (all)  row r-1: Sraw_i = sum_j (a alpha)_ij rt_j  -> LDS: rt_i Sraw_i
-//             G_i(y) = grad rho_i from the register ring
+//   1  (all)  moments of row r -> LDS: rt_i, j_i;  G_i(y) = grad rho_i
+//      (helpers A, B) row r-1 mixture coefficients of RT ln f_i   (Eq. (9)-(12))
 //   -- barrier --
-//   M  (one wave, rotating)  row r: rt, b_m rt, s, rho, j totals -> LDS rings
-//             row r-1: a_m and the three mixture coefficients of
-//             RT ln f_i = RT ln(rt_i c1) + b_i c2 - c3 Sraw_i      (Eq. (9)-(12))
+//   2  (all)  s(r) = sum_j sqrt(kappa_j) rt_j;  psi_i(r-1) = RT ln f_i -
+//             sqrt(kappa_i) lap s  (Eq. (3)-(5));  F_i(y) = -rt_i grad psi_i
+//             -> LDS;  Sraw_i(r) = sum_j (a alpha)_ij rt_j -> LDS
+//      (helpers) row r totals: rt, b_m rt, 1/rho, j -> LDS rings
 //   -- barrier --
-//   C  (all)  psi_i(r-1) = RT ln f_i - sqrt(kappa_i) lap s     (Eq. (3)-(5))
-//   D  (all)  F_i(y) = -rt_i grad psi_i                 -> LDS
-//   -- barrier --
-//   E  (all)  u(y) = (j + F/2) / rho, collide row y (Eq. (1)), push-store
+//   3  (all)  u(y) = (j + F/2) / rho, collide row y (Eq. (1)), push-store
 //
 // Every population is read from HBM once per step; the 4 halo columns and
 // the 4 warm-up rows of a work item are re-reads that neighbouring items
@@ -37,13 +34,13 @@ template <class T> using gmptr = __attribute__((address_space(1))) T *;
 // or lane l+1 (wave_shl:1).  Lanes 0 / 63 receive 0; only lanes 1..62 use
 // shifted values.
 __device__ __forceinline__ double from_left(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_right(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -67,18 +64,59 @@ __device__ __forceinline__ double lap3(double S, double C, double N) {
     return 6.0 * ((1.0 / 9.0) * ax + (1.0 / 36.0) * dg);
 }
 
+// Wave that computes part p (0..3) of the per-site sums.  Waves of a
+// workgroup are dealt to the 4 SIMDs of a CU in turn, so with NC % 4 != 0
+// the SIMDs s >= NC % 4 hold one wave fewer; the parts go to their waves.
+template <int NC>
+__device__ constexpr int helper_wave(int p) {
+    int light[16] = {0};
+    int n = 0;
+    for (int w = 0; w < NC; ++w)
+        if (NC % 4 == 0 || w % 4 >= NC % 4) light[n++] = w;
+    if (n == 0)
+        for (int w = 0; w < NC; ++w) light[n++] = w;
+    return light[p % n];
+}
+
+// D2Q9 collision of one component at one site, Eq. (1a)-(1c) with
+// rho^c = 0 and cs^2 = 1/3, factored per opposite pair of directions:
+//   g*_a = (1 - omega) g_a + w_a T_a,
+//   T_a  = omega geq_a / w_a + c F_a / w_a
+//        = eu (A + B eu + 9c eF + 3c eG) + 3c eF + K(|e_a|^2),
+//   A = 3 omega rho, B = 4.5 omega rho, c = 1 - 1/(2 tau),
+//   K(e2) = -1.5 omega rho u.u - 3c F.u + c (1.5 e2 - 2) G.u,
+// and g*_0 = (1 - omega) g_0 + omega rho + w_0 K(0).  For the pair +e / -e
+// with P = B eu + 9c eF + 3c eG:  T+ = eu (A + P) + 3c eF + K,
+// T- = eu (P - A) - 3c eF + K.
+__device__ __forceinline__ void collide_pair(double A, double B, double C9, double C3, double K,
+                                             double eu, double eF, double eG, double &tp,
+                                             double &tm) {
+    const double P = fma(C3, eG, fma(C9, eF, B * eu));
+    tp = fma(eu, A + P, fma(C3, eF, K));
+    tm = fma(eu, P - A, fma(-C3, eF, K));
+}
+
 template <int NC>
 struct FusedLds {
-    double rt[2][NC][64];   // molar densities of rows r-1, r (slot = row & 1)
+    double rt[NC][64];      // molar densities of row r
     double jx[NC][64];      // per-component momentum of row r
     double jy[NC][64];
-    double xs[NC][64];      // rt_i Sraw_i of row r-1
+    double xs[NC][64];      // rt_i Sraw_i of row r
     double fx[NC][64];      // per-component force of row y
     double fy[NC][64];
-    double tot[4][4][64];   // ring over rows (slot = row & 3): s, rho, jx, jy
+    double tot[4][3][64];   // ring over rows (slot = row & 3): 1/rho, jx, jy
     double mx[2][2][64];    // ring over rows (slot = row & 1): rt, b_m rt
-    double eos[3][64];      // c1, c2, c3 of row r-1
+    double eos[5][64];      // row r-1: c1, c2a, c2b, c3b (helper A), lambda (helper B)
 };
+
+// 1/x to ~1 ulp: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 
 template <int NC, typename ST>
 struct Fused {
@@ -87,30 +125,35 @@ struct Fused {
     gptr<ST> src[9];
     gmptr<ST> dst[9];
     int comp, lane, nx, ny, xc, xm, xp, y0, rows;
+    int wm3, wm2, wm1, w0;   // wrapped row indices of rows r-3 .. r (uniform)
     bool outl;
-    double invM, bi, sqki, rb, RT, omega, fcoef;
+    double invM, bi, sqki, rb, RT, invRT, omega, fcoef;
     uint32_t bad;
 
-    __device__ __forceinline__ int wrap_row(int r) const {
-        r %= ny;
-        return r < 0 ? r + ny : r;
-    }
-
-    __device__ __forceinline__ void load_row(ST (&g)[9], int r) const {
-        const uint32_t off = (uint32_t)(wrap_row(r) * nx + xc);
+    __device__ __forceinline__ void load_row(ST (&g)[9], int wrow) const {
+        const uint32_t off = (uint32_t)(wrow * nx + xc);
 #pragma unroll
         for (int a = 0; a < 9; ++a) g[a] = src[a][off];
     }
 
-    // One lead row r.  gA = row r-2 (collided), gB = row r-1, gC = row r
-    // (loaded), gD = row r+1 (prefetched here).  rh* = rho_i of rows
-    // r-3 .. r, ps* = psi_i of rows r-3 .. r-1 (written here).
+    // One lead row r.  gA = row r-2 (collided), gC = row r (loaded), gD =
+    // row r+1 (prefetched here).  rh* = rho_i of rows r-3 .. r (rh0 written
+    // here), ps* = psi_i of rows r-3 .. r-1 (psm1 written here), sv* = s of
+    // rows r-2 .. r (sv0 written here), sn / so = Sraw_i of rows r / r-1.
     __device__ __forceinline__ void body(int r, int rend, ST (&gA)[9], ST (&gC)[9], ST (&gD)[9],
                                          double rhm3, double rhm2, double rhm1, double &rh0,
-                                         double psm3, double psm2, double &psm1) {
-        const int slot = r & 1;
-        if (r < rend) load_row(gD, r + 1);
-        // ---- A: moments of row r
+                                         double psm3, double psm2, double &psm1, double svm2,
+                                         double svm1, double &sv0, double &sn, double so) {
+        // advance the wrapped row indices (uniform, scalar)
+        wm3 = wm2;
+        wm2 = wm1;
+        wm1 = w0;
+        w0 = (r == y0 - 2) ? w0 : (w0 + 1 == ny ? 0 : w0 + 1);
+        if (r < rend) load_row(gD, w0 + 1 == ny ? 0 : w0 + 1);
+        const bool do_s = r >= y0 - 1;
+        const bool do_eos = r >= y0;
+        const bool do_out = r >= y0 + 2;
+        // ---- phase 1: moments of row r; G_i of row y; mixture terms of row r-1
         {
             double v[9];
 #pragma unroll
@@ -120,82 +163,59 @@ struct Fused {
 #pragma unroll
             for (int a = 0; a < 9; ++a) rho += v[a];
             rh0 = rho;
-            L.rt[slot][comp][lane] = rho * invM;
+            L.rt[comp][lane] = rho * invM;
             L.jx[comp][lane] = (v[1] - v[3]) + (v[5] - v[7]) + (v[8] - v[6]);
             L.jy[comp][lane] = (v[2] - v[4]) + (v[5] - v[7]) + (v[6] - v[8]);
         }
-        // ---- B: Sraw_i of row r-1; G_i of row y
-        const bool do_eos = r >= y0;
-        const bool do_out = r >= y0 + 2;
-        double Sraw = 0.0;
-        if (do_eos) {
-            cptr<double> arow = C->aij + comp * FUG_MAXC;
-#pragma unroll
-            for (int j = 0; j < NC; ++j) Sraw += arow[j] * L.rt[slot ^ 1][j][lane];
-            L.xs[comp][lane] = rhm1 * invM * Sraw;
-        }
         double Gx = 0.0, Gy = 0.0;
         if (do_out) grad3(rhm3, rhm2, rhm1, Gx, Gy);
-        __syncthreads();
-        // ---- M: one wave computes the per-site sums over components
-        if (comp == ((r % NC) + NC) % NC) {
-            double rtt = 0.0, eta = 0.0, sv = 0.0, rtot = 0.0, jxt = 0.0, jyt = 0.0;
+        // Eq. (9)-(12) in combined-log form for row r-1,
+        //   RT ln f_i = RT ln(rt_i c1) + b_i (c2a + lambda c2b) - lambda c3b Sraw_i,
+        // split over two helper waves: A (reciprocals, Z - 1) and B (lambda).
+        if (do_eos && comp == helper_wave<NC>(0)) {
+            const int ms = (r - 1) & 1;
+            const double rt1 = L.mx[ms][0][lane];
+            const double et1 = L.mx[ms][1][lane];
+            double xsum = 0.0;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                const double t = L.rt[slot][j][lane];
-                rtt += t;
-                eta += C->b[j] * t;
-                sv += C->sqk[j] * t;
-                rtot += C->M[j] * t;
-                jxt += L.jx[j][lane];
-                jyt += L.jy[j][lane];
-            }
-            const int ts = r & 3;
-            L.tot[ts][0][lane] = sv;
-            L.tot[ts][1][lane] = rtot;
-            L.tot[ts][2][lane] = jxt;
-            L.tot[ts][3][lane] = jyt;
-            L.mx[slot][0][lane] = rtt;
-            L.mx[slot][1][lane] = eta;
-            if (do_eos) {
-                // mixture terms of row r-1 (Eq. (9)-(12), combined-log form)
-                const double rt1 = L.mx[slot ^ 1][0][lane];
-                const double et1 = L.mx[slot ^ 1][1][lane];
-                double xsum = 0.0;
-#pragma unroll
-                for (int j = 0; j < NC; ++j) xsum += L.xs[j][lane];
-                const double inv_rt = 1.0 / rt1;
-                const double am = xsum * inv_rt * inv_rt;
-                const double ome = 1.0 - et1;
-                if (!(ome > 0.0)) bad |= FUG_ST_COVOLUME;
-                const double inv_ome = 1.0 / ome;
-                const double inv_bm = rt1 / et1;
-                const double den = 1.0 + 2.0 * et1 - et1 * et1;
-                const double zm1 = et1 * inv_ome - am * rt1 / (RT * den);
-                const double s2 = 1.4142135623730951;
-                const double lam =
-                    log((1.0 + (1.0 + s2) * et1) / (1.0 + (1.0 - s2) * et1));
-                const double lam_c = lam * inv_bm * (0.5 / s2);
-                L.eos[0][lane] = RT * inv_ome;                       // c1
-                L.eos[1][lane] = RT * inv_bm * zm1 + lam_c * am * inv_bm;  // c2
-                L.eos[2][lane] = 2.0 * lam_c * inv_rt;               // c3
-            }
+            for (int j = 0; j < NC; ++j) xsum += L.xs[j][lane];
+            const double inv_rt = frcp(rt1);
+            const double am = xsum * inv_rt * inv_rt;
+            const double ome = 1.0 - et1;
+            if (!(ome > 0.0)) bad |= FUG_ST_COVOLUME;
+            const double inv_ome = frcp(ome);
+            const double inv_bm = rt1 * frcp(et1);
+            const double den = 1.0 + 2.0 * et1 - et1 * et1;
+            const double zm1 = et1 * inv_ome - am * rt1 * invRT * frcp(den);
+            const double k = 0.35355339059327373;   // 1 / (2 sqrt 2)
+            L.eos[0][lane] = RT * inv_ome;
+            L.eos[1][lane] = RT * zm1 * inv_bm;
+            L.eos[2][lane] = k * am * inv_bm * inv_bm;
+            L.eos[3][lane] = 2.0 * k * inv_bm * inv_rt;
+        }
+        if (do_eos && comp == helper_wave<NC>(1)) {
+            const double et1 = L.mx[(r - 1) & 1][1][lane];
+            const double s2 = 1.4142135623730951;
+            L.eos[4][lane] = log((1.0 + (1.0 + s2) * et1) * frcp(1.0 + (1.0 - s2) * et1));
         }
         __syncthreads();
-        // ---- C: psi_i of row r-1
+        // ---- phase 2: s(r); psi_i(r-1); F_i(y); Sraw_i(r); helper sums of row r
+        {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc += C->sqk[j] * L.rt[j][lane];
+            sv0 = acc;
+        }
         if (do_eos) {
-            const double c1 = L.eos[0][lane], c2 = L.eos[1][lane], c3 = L.eos[2][lane];
+            const double c1 = L.eos[0][lane], c2a = L.eos[1][lane], c2b = L.eos[2][lane];
+            const double c3b = L.eos[3][lane], lam = L.eos[4][lane];
             const double rti = rhm1 * invM;
-            const double lnf = RT * log(rti * c1) + bi * c2 - c3 * Sraw;
-            const double s_m2 = L.tot[(r - 2) & 3][0][lane];
-            const double s_m1 = L.tot[(r - 1) & 3][0][lane];
-            const double s_0 = L.tot[r & 3][0][lane];
-            const double psi = lnf - sqki * lap3(s_m2, s_m1, s_0);
+            const double lnf = RT * log(rti * c1) + bi * fma(lam, c2b, c2a) - lam * c3b * so;
+            const double psi = lnf - sqki * lap3(svm2, svm1, sv0);
             psm1 = psi;
             if (!(rti > 0.0)) bad |= FUG_ST_NEGATIVE;
             if (!isfinite(psi)) bad |= FUG_ST_NONFINITE;
         }
-        // ---- D: force of row y
         double Fx = 0.0, Fy = 0.0;
         if (do_out) {
             double gx, gy;
@@ -206,8 +226,39 @@ struct Fused {
             L.fx[comp][lane] = Fx;
             L.fy[comp][lane] = Fy;
         }
+        if (do_s) {
+            cptr<double> arow = C->aij + comp * FUG_MAXC;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc += arow[j] * L.rt[j][lane];
+            sn = acc;
+            L.xs[comp][lane] = rh0 * invM * acc;
+        }
+        if (do_s && comp == helper_wave<NC>(2)) {
+            double rtt = 0.0, eta = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const double t = L.rt[j][lane];
+                rtt += t;
+                eta += C->b[j] * t;
+            }
+            L.mx[r & 1][0][lane] = rtt;
+            L.mx[r & 1][1][lane] = eta;
+        }
+        if (comp == helper_wave<NC>(3)) {
+            double rtot = 0.0, jxt = 0.0, jyt = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                rtot += C->M[j] * L.rt[j][lane];
+                jxt += L.jx[j][lane];
+                jyt += L.jy[j][lane];
+            }
+            L.tot[r & 3][0][lane] = frcp(rtot);
+            L.tot[r & 3][1][lane] = jxt;
+            L.tot[r & 3][2][lane] = jyt;
+        }
         __syncthreads();
-        // ---- E: velocity, collision and push of row y
+        // ---- phase 3: velocity, collision and push of row y
         if (do_out) {
             double Fsx = 0.0, Fsy = 0.0;
 #pragma unroll
@@ -216,30 +267,38 @@ struct Fused {
                 Fsy += L.fy[j][lane];
             }
             const int ys = (r - 2) & 3;
-            const double inv_rho = 1.0 / L.tot[ys][1][lane];
-            const double ux = (L.tot[ys][2][lane] + 0.5 * Fsx) * inv_rho;
-            const double uy = (L.tot[ys][3][lane] + 0.5 * Fsy) * inv_rho;
-            const double uu = ux * ux + uy * uy;
-            const double Fu = Fx * ux + Fy * uy;
+            const double inv_rho = L.tot[ys][0][lane];
+            const double ux = (L.tot[ys][1][lane] + 0.5 * Fsx) * inv_rho;
+            const double uy = (L.tot[ys][2][lane] + 0.5 * Fsy) * inv_rho;
+            const double orho = omega * rhm2;
+            const double A = 3.0 * orho, B = 4.5 * orho;
+            const double C9 = 9.0 * fcoef, C3 = 3.0 * fcoef;
+            const double omc = 1.0 - omega;
+            const double base = -1.5 * orho * (ux * ux + uy * uy) - C3 * (Fx * ux + Fy * uy);
             const double Gu = Gx * ux + Gy * uy;
-            const double rho = rhm2;
-            const int y = r - 2;
-            const uint32_t rowm = (uint32_t)(wrap_row(y - 1) * nx);
-            const uint32_t row0 = (uint32_t)(wrap_row(y) * nx);
-            const uint32_t rowp = (uint32_t)(wrap_row(y + 1) * nx);
+            const double K1 = fma(-0.5 * fcoef, Gu, base);
+            const double K2 = fma(fcoef, Gu, base);
+            const uint32_t rowm = (uint32_t)(wm3 * nx);
+            const uint32_t row0 = (uint32_t)(wm2 * nx);
+            const uint32_t rowp = (uint32_t)(wm1 * nx);
             if (outl) {
-#pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    double gv = (double)gA[a];
-                    if (a == 0) gv += rb;
-                    double o = collide_one<D2Q9>(a, gv, rho, ux, uy, 0.0, Fx, Fy, 0.0, Gx, Gy,
-                                                 0.0, uu, Fu, Gu, omega, fcoef);
-                    if (a == 0) o -= rb;
-                    const int exa = D2Q9::ex(a), eya = D2Q9::ey(a);
-                    const uint32_t xx = (uint32_t)(exa == 0 ? xc : (exa > 0 ? xp : xm));
-                    const uint32_t rr = eya == 0 ? row0 : (eya > 0 ? rowp : rowm);
-                    dst[a][rr + xx] = (ST)o;
-                }
+                // rest population and the four opposite pairs, stored as they are formed
+                dst[0][row0 + xc] =
+                    (ST)(fma(omc, (double)gA[0] + rb,
+                             fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho)) - rb);
+                double tp, tm;
+                collide_pair(A, B, C9, C3, K1, ux, Fx, Gx, tp, tm);
+                dst[1][row0 + xp] = (ST)fma(omc, (double)gA[1], (1.0 / 9.0) * tp);
+                dst[3][row0 + xm] = (ST)fma(omc, (double)gA[3], (1.0 / 9.0) * tm);
+                collide_pair(A, B, C9, C3, K1, uy, Fy, Gy, tp, tm);
+                dst[2][rowp + xc] = (ST)fma(omc, (double)gA[2], (1.0 / 9.0) * tp);
+                dst[4][rowm + xc] = (ST)fma(omc, (double)gA[4], (1.0 / 9.0) * tm);
+                collide_pair(A, B, C9, C3, K2, ux + uy, Fx + Fy, Gx + Gy, tp, tm);
+                dst[5][rowp + xp] = (ST)fma(omc, (double)gA[5], (1.0 / 36.0) * tp);
+                dst[7][rowm + xm] = (ST)fma(omc, (double)gA[7], (1.0 / 36.0) * tm);
+                collide_pair(A, B, C9, C3, K2, uy - ux, Fy - Fx, Gy - Gx, tp, tm);
+                dst[6][rowp + xm] = (ST)fma(omc, (double)gA[6], (1.0 / 36.0) * tp);
+                dst[8][rowm + xp] = (ST)fma(omc, (double)gA[8], (1.0 / 36.0) * tm);
             }
         }
     }
@@ -282,27 +341,48 @@ __global__ __launch_bounds__(64 * NC) void k_fused_d2q9(const FusedItem *__restr
     f.sqki = C->sqk[f.comp];
     f.rb = C->rhobar[f.comp];
     f.RT = C->RT;
+    f.invRT = 1.0 / C->RT;
     f.omega = C->omega;
     f.fcoef = C->fcoef;
     f.bad = 0;
+    const int rbeg = it.y0 - 2, rend = it.y0 + it.rows + 1;
+    {
+        int w = rbeg % f.ny;
+        if (w < 0) w += f.ny;
+        f.w0 = w;           // body() keeps w0 for its first row, then advances
+        f.wm1 = f.wm2 = f.wm3 = 0;
+    }
 
     ST g0[9], g1[9], g2[9], g3[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) g0[a] = g1[a] = g3[a] = (ST)0;
-    const int rbeg = it.y0 - 2, rend = it.y0 + it.rows + 1;
-    f.load_row(g2, rbeg);
-    // rho rings (rows r-3..r) and psi rings (rows r-3..r-1), rotated by phase
+    f.load_row(g2, f.w0);
+    // register rings: g0..g3 = populations of rows r-2 .. r+1; h = rho_i of
+    // rows r-3 .. r; p = psi_i of rows r-3 .. r-1; s = s of rows r-2 .. r;
+    // q = Sraw_i of rows r-1, r.  (A rolled loop with ring moves keeps the
+    // register pressure low enough for three waves per SIMD.)
     double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
-    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-    for (int r = rbeg; r <= rend; r += 4) {
-        // phase 0: rows r-2,r-1,r,r+1 in g0,g1,g2,g3; rho r-3..r in h1,h2,h3,h0
-        f.body(r, rend, g0, g2, g3, h1, h2, h3, h0, p1, p2, p3);
-        if (r + 1 > rend) break;
-        f.body(r + 1, rend, g1, g3, g0, h2, h3, h0, h1, p2, p3, p0);
-        if (r + 2 > rend) break;
-        f.body(r + 2, rend, g2, g0, g1, h3, h0, h1, h2, p3, p0, p1);
-        if (r + 3 > rend) break;
-        f.body(r + 3, rend, g3, g1, g2, h0, h1, h2, h3, p0, p1, p2);
+    double p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    double qn = 0.0, qo = 0.0;
+    for (int r = rbeg; r <= rend; ++r) {
+        f.body(r, rend, g0, g2, g3, h1, h2, h3, h0, p1, p2, p3, s1, s2, s0, qn, qo);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const ST t = g0[a];
+            g0[a] = g1[a];
+            g1[a] = g2[a];
+            g2[a] = g3[a];
+            g3[a] = t;
+        }
+        h1 = h2;
+        h2 = h3;
+        h3 = h0;
+        p1 = p2;
+        p2 = p3;
+        s1 = s2;
+        s2 = s0;
+        qo = qn;
     }
     if (f.bad) atomicOr(sm->status, f.bad);
 }
@@ -319,7 +399,39 @@ hipError_t launch_nc(bool fp32, const FusedItem *items, int nitems, const FusedS
     return hipGetLastError();
 }
 
+template <int NC>
+int occ_nc(bool fp32) {
+    int nb = 0;
+    hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb, (const void *)k_fused_d2q9<NC, float>, 64 * NC, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb, (const void *)k_fused_d2q9<NC, double>, 64 * NC, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
 }  // namespace
+
+int fused_blocks_per_cu(int ncomp, bool fp32) {
+    switch (ncomp) {
+        case 1: return occ_nc<1>(fp32);
+        case 2: return occ_nc<2>(fp32);
+        case 3: return occ_nc<3>(fp32);
+        case 4: return occ_nc<4>(fp32);
+        case 5: return occ_nc<5>(fp32);
+        case 6: return occ_nc<6>(fp32);
+        case 7: return occ_nc<7>(fp32);
+        case 8: return occ_nc<8>(fp32);
+        case 9: return occ_nc<9>(fp32);
+        case 10: return occ_nc<10>(fp32);
+        case 11: return occ_nc<11>(fp32);
+        case 12: return occ_nc<12>(fp32);
+        case 13: return occ_nc<13>(fp32);
+        case 14: return occ_nc<14>(fp32);
+        case 15: return occ_nc<15>(fp32);
+        case 16: return occ_nc<16>(fp32);
+        default: return 1;
+    }
+}
 
 hipError_t launch_fused_d2q9(int ncomp, bool fp32, const FusedItem *items, int nitems,
                              const FusedSim *sims, int flip, hipStream_t st) {

@@ -244,8 +244,9 @@ __global__ __launch_bounds__(TPB) void k_velocity(const SimConst *__restrict__ c
 }
 
 // Diagnostics: per-block partial sums over a fixed site assignment
-// (block b, thread t handle sites t + TPB*(b + nblk*k)); the host adds the
-// block partials in block order, so the result is bitwise reproducible.
+// (block b, thread t handle sites t + TPB*(b + nblk*k)), one pass over the
+// populations; the host adds the block partials in block order, so the
+// result is bitwise reproducible.
 // part[b][0..N) mass, [N..2N) sum |rho_i - snap_i|, [2N..2N+3) momentum.
 template <class L, typename ST>
 __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
@@ -257,33 +258,39 @@ __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
     const int N = c->N;
     const int nq = 2 * N + 3;
     const int64_t stride = (int64_t)gridDim.x * TPB;
-    for (int q = 0; q < nq; ++q) {
-        double acc = 0.0;
-        for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < ns; s += stride) {
-            if (q < 2 * N) {
-                const int i = q < N ? q : q - N;
+    double mass[FUG_MAXC], res[FUG_MAXC], mom[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < FUG_MAXC; ++i) mass[i] = res[i] = 0.0;
+    for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < ns; s += stride) {
+#pragma unroll
+        for (int i = 0; i < FUG_MAXC; ++i) {
+            if (i < N) {
                 double r = 0.0;
 #pragma unroll
-                for (int a = 0; a < L::Q; ++a) r += ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
+                for (int a = 0; a < L::Q; ++a) {
+                    const double v = ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
+                    r += v;
+                    mom[0] += L::ex(a) * v;
+                    mom[1] += L::ey(a) * v;
+                    mom[2] += L::ez(a) * v;
+                }
                 r += c->rhobar[i];
-                if (q < N) {
-                    acc += r;
-                } else {
-                    if (use_snap) acc += fabs(r - snap[(int64_t)i * ns + s]);
-                    snap[(int64_t)i * ns + s] = r;
-                }
-            } else {
-                const int d = q - 2 * N;
-                for (int i = 0; i < N; ++i) {
-#pragma unroll
-                    for (int a = 1; a < L::Q; ++a) {
-                        const int e = d == 0 ? L::ex(a) : (d == 1 ? L::ey(a) : L::ez(a));
-                        if (e != 0) acc += e * ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
-                    }
-                }
+                mass[i] += r;
+                double *sp = snap + (int64_t)i * ns + s;
+                if (use_snap) res[i] += fabs(r - *sp);
+                *sp = r;
             }
         }
-        red[threadIdx.x] = acc;
+    }
+    for (int q = 0; q < nq; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < FUG_MAXC; ++i) {
+            if (q == i) v = mass[i];
+            if (q == N + i) v = res[i];
+        }
+        if (q >= 2 * N) v = mom[q - 2 * N];
+        red[threadIdx.x] = v;
         __syncthreads();
         for (int w = TPB / 2; w > 0; w >>= 1) {
             if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
