@@ -84,6 +84,124 @@ def time_gpu(precision, steps, warmup, n, diag_every=100):
     return res
 
 
+def sweep_leg(steps=512, acc_steps=20000, acc_count=8):
+    """Batched ternary sweep (256 C1/C3/nC10 instances, FP32 storage, one
+    launch per step, graph-replayed) against the same instances stepped one
+    after another in plain FP64; accuracy of FP32 storage on a subset run to
+    acc_steps."""
+    import torch
+    from paper_2306_10652_amd import batch, capi
+    from inputs import fields as Fi
+    S = Fi.load_phase_states()["ternary_sweep"]
+    specs = batch.ternary_specs(S)
+    st = torch.cuda.Stream()
+    a = batch.Sweep(specs, capi.FP32_STORAGE, stream=st)
+    a.step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.step(steps)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    csu = a.csu_per_step
+    a.close()
+    b = batch.Sweep(specs, capi.FP64, stream=st)
+    b.step_sequential(8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step_sequential(steps // 4)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    b.close()
+    # accuracy on a subset
+    sub = specs[:acc_count]
+    a = batch.Sweep(sub, capi.FP32_STORAGE, stream=st)
+    b = batch.Sweep(sub, capi.FP64, stream=st)
+    a.step(acc_steps)
+    b.step(acc_steps)
+    er, ex = 0.0, 0.0
+    for pa, pb in zip(a.phases(), b.phases()):
+        er = max(er, abs(pa["rho_V"] / pb["rho_V"] - 1), abs(pa["rho_L"] / pb["rho_L"] - 1))
+        ex = max(ex, float(np.max(np.abs(pa["x"] - pb["x"]))), float(np.max(np.abs(pa["y"] - pb["y"]))))
+    a.close()
+    b.close()
+    v_a = csu * steps / ta
+    v_b = csu * (steps // 4) / tb
+    return dict(instances=len(specs), csu_per_step=csu,
+                fp32_batched=dict(value=round(v_a, 1), unit="CSU/s", ms_per_step=round(ta / steps * 1e3, 4)),
+                fp64_sequential=dict(value=round(v_b, 1), unit="CSU/s",
+                                     ms_per_step=round(tb / (steps // 4) * 1e3, 4)),
+                factor=round(v_a / v_b, 2),
+                fp32_vs_fp64=dict(instances=acc_count, steps=acc_steps, max_rel_phase_density=er,
+                                  max_abs_mole_fraction=ex))
+
+
+def time_vs_n_leg(steps=2000):
+    """Per-step time against component count: Table II cases 1-6 as
+    256 x 32 flat slabs, FP64 (the paper reports linear growth in N)."""
+    import torch
+    from paper_2306_10652_amd import capi
+    from inputs import components as C
+    from inputs import fields as Fi
+    S = Fi.load_phase_states()
+    Ns, us = [], []
+    st = torch.cuda.Stream()
+    for case in range(1, 7):
+        comps, T, _ = C.table_ii_components(case)
+        v = S["vle%d" % case]
+        rho = Fi.slab(256, 32, v["rho_V"], v["rho_L"], 0.5)
+        mix = capi.Mixture.from_components(comps, T)
+        sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (256, 32), rho, stream=st)
+        sim.step_n(256)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step_n(steps)
+        torch.cuda.synchronize()
+        us.append((time.perf_counter() - t0) / steps * 1e6)
+        Ns.append(len(comps))
+        sim.close()
+    A = np.vstack([Ns, np.ones(len(Ns))]).T
+    coef, *_ = np.linalg.lstsq(A, np.array(us), rcond=None)
+    fit = A @ coef
+    r2 = 1 - np.sum((np.array(us) - fit) ** 2) / np.sum((np.array(us) - np.mean(us)) ** 2)
+    return dict(grid=[256, 32], N=Ns, us_per_step=[round(u, 2) for u in us],
+                slope_us_per_component=round(coef[0], 3), r2=round(float(r2), 4))
+
+
+def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=None):
+    """Continuous batching: Poisson arrivals of requests from the stored pool
+    (2-10 components; D2Q9 up to 256^2, D3Q19 up to 64^3 here so the leg
+    stays within a minute), FP32 storage, run to residual tol.  The arrival
+    rate offers `load` x the measured batched throughput, using the mean work
+    of calibration requests served alone."""
+    import torch
+    from paper_2306_10652_amd import capi, serve
+    from inputs import fields as Fi
+    S = Fi.load_phase_states()["serving_pool"]
+    calib = serve.pool_requests(S, 4, rate_hz=1e6, tol=tol, max_steps=max_steps,
+                                max_n2d=256, max_n3d=64)
+    work = []
+    for r in calib:
+        r.arrival = 0.0
+        serve.Server(64 << 30).run([r])
+        work.append(r.csu())
+    mean_work = float(np.mean(work))
+    cap = capacity_csu_s or 2.0e10
+    rate = load * cap / mean_work
+    reqs = serve.pool_requests(S, count, rate_hz=rate, tol=tol, max_steps=max_steps,
+                               max_n2d=256, max_n3d=64, seed=55)
+    srv = serve.Server(64 << 30, chunk=200)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    st = serve.latency_stats(done)
+    csu = sum(r.csu() for r in done if r.status == 0)
+    st.update(requests=count, offered_load=load, arrival_rate_hz=round(rate, 3),
+              hbm_budget_gb=64, tol=tol, max_steps=max_steps, wall_s=round(wall, 3),
+              throughput=dict(value=round(csu / wall, 1), unit="CSU/s"),
+              failed=int(sum(r.status != 0 for r in done)))
+    return st
+
+
 def cpu_baseline(n, budget_s=15.0):
     """The CPU oracle on a bounded sample: whole 1024^2 steps until ~budget."""
     from oracle.lbm import OracleLBM, oracle_mixture, build_oracle
@@ -123,6 +241,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the sweep, time-vs-N and serving legs")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -159,7 +279,8 @@ def main():
                 unit="GB/s", frac=round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4),
                 traffic=traffic, alg_bytes_per_launch=r64["alg_bytes"],
                 launch_ms=round(r64["launch_ms"], 5), kernel="k_fused_d2q9<10,double>")
-    out = dict(metric="component-site updates/s & %HBM roofline", value=round(r64["csu"], 1),
+    out = dict(metric="component-site updates/s & %HBM roofline; p50/p99 time-to-equilibrium",
+               value=round(r64["csu"], 1),
                unit="CSU/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=round(r64["ms_per_step"], 5), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
@@ -173,6 +294,11 @@ def main():
                                  alg_bytes_per_launch=r32["alg_bytes"],
                                  launch_ms=round(r32["launch_ms"], 5)),
                status=[r64["status"], r32["status"]])
+    if not args.no_extra:
+        out["batched_sweep"] = sweep_leg()
+        out["time_vs_N"] = time_vs_n_leg()
+        out["serving"] = serving_leg(
+            capacity_csu_s=out["batched_sweep"]["fp32_batched"]["value"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_budget)
     print(json.dumps(out), flush=True)

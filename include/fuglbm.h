@@ -28,8 +28,11 @@
  *    thread-safe: use one handle from one thread at a time.
  *  - Populations are stored component-major, g[i][a][site] with
  *    site = x + nx*(y + ny*z), two buffers swapped every step.  FP32 storage
- *    keeps g_{a,i} - rhobar_i*delta_{a0} in float, rhobar_i being the
- *    per-component domain mean at init (FP64); arithmetic stays FP64.
+ *    keeps the rest populations g_{0,i} in FP64 (first, [ncomp][sites]) and
+ *    the moving ones g_{a,i}, a >= 1, in FP32 (then [ncomp][Q-1][sites]);
+ *    each step folds the FP32 rounding error of a site's moving populations
+ *    into its rest population, so component masses are conserved to FP64
+ *    rounding.  Arithmetic is FP64 in both precisions.
  */
 #ifndef FUGLBM_H
 #define FUGLBM_H
@@ -149,7 +152,8 @@ fuglbm_status fuglbm_read_moments(fuglbm_sim *sim, double *rho_out, double *u_ou
 fuglbm_status fuglbm_diagnostics(fuglbm_sim *sim, fuglbm_diag *diag);
 
 /* Checkpoint / restore the raw populations, host [ncomp][Q][sites] FP64
- * (FP32 storage is widened / rounded; the rest-direction offset is applied). */
+ * (with FP32 storage the moving populations are widened / rounded to
+ * nearest; the rest populations are FP64 either way). */
 fuglbm_status fuglbm_read_populations(fuglbm_sim *sim, double *g_out);
 fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int64_t step);
 

@@ -49,6 +49,24 @@ def two_phase_state(comps, T, p_bar, z, kij=None):
                 rho_uniform=list(om.M * np.asarray(z) / np.sum(z) * rho_tot))
 
 
+def stable_in_oracle(comps, T, rho_V, rho_L, S_V, n, lattice=0, kij=None, steps=2000):
+    """Screen a draw: the oracle advances a thin slab of the draw's own width
+    (n x 2, or n x 2 x 2 for D3Q19) for `steps` steps without leaving the
+    EOS domain.  High vapour/liquid density ratios with nearly absent heavy
+    components make the scheme unstable at tau = 1; such draws are rejected."""
+    from inputs import fields as Fi
+    from oracle.lbm import OracleLBM
+    m = oracle_mixture(comps, T, kij)
+    nz = 2 if lattice == 1 else 1
+    rho = Fi.slab(n, 2, rho_V, rho_L, S_V, nz=nz)
+    o = OracleLBM(m, lattice, (n, 2, nz) if lattice == 1 else (n, 2), rho)
+    for _ in range(steps // 250):
+        if o.run(250) != 0:
+            return False
+    rr = o.rho()
+    return bool(np.all(np.isfinite(rr)) and np.all(rr > 0))
+
+
 def comp_list(comps):
     return [c._asdict() for c in comps]
 
@@ -69,6 +87,8 @@ def ternary_sweep(n_inst=256, seed=3):
         if st is None or not (0.1 <= st["S_V"] <= 0.9):
             continue
         if np.max(np.abs(np.array(st["x"]) - np.array(st["y"]))) < 0.05:
+            continue
+        if not stable_in_oracle(comps, T, st["rho_V"], st["rho_L"], st["S_V"], n):
             continue
         st.update(n=n, T=T, p_bar_in=p, z=list(z))
         out.append(st)
@@ -93,6 +113,9 @@ def serving_pool(n_req=160, seed=5):
         if st is None or not (0.2 <= st["S_V"] <= 0.8):
             continue
         if np.max(np.abs(np.array(st["x"]) - np.array(st["y"]))) < 0.05:
+            continue
+        if not stable_in_oracle(comps, T, st["rho_V"], st["rho_L"], st["S_V"], n,
+                                lattice=1 if three_d else 0):
             continue
         st.update(N=N, lattice="D3Q19" if three_d else "D2Q9", n=n, T=T, p_bar_in=p,
                   z=list(z), arrival_u=float(rng.uniform()))

@@ -98,7 +98,8 @@ static Carve carve(int N, int lat, bool fp32, int nx, int ny, int nz) {
     Carve c{};
     const int64_t ns = (int64_t)nx * ny * nz;
     const int Q = lattice_Q(lat), D = lattice_D(lat);
-    const size_t pop = align256((size_t)N * Q * ns * (fp32 ? 4 : 8));
+    const size_t pop = align256((size_t)(fp32 ? pop_buffer_bytes<float>(N, Q, ns)
+                                              : pop_buffer_bytes<double>(N, Q, ns)));
     size_t o = 0;
     c.buf0 = o; o += pop;
     c.buf1 = o; o += pop;
@@ -115,7 +116,7 @@ static Carve carve(int N, int lat, bool fp32, int nx, int ny, int nz) {
     c.max_items = 0;
     if (lat == 0) {
         const int strips = (nx + FUSED_OUT - 1) / FUSED_OUT;
-        c.max_items = strips * ((ny + 7) / 8) + 8;
+        c.max_items = strips * ny + 8;   // rows >= 1 per item
     }
     c.items = o; o += align256((size_t)c.max_items * sizeof(FusedItem));
     c.total = o;
@@ -155,7 +156,13 @@ struct fuglbm_sim {
     uint32_t sticky;
     hipStream_t last_stream;
     GraphCache graph;
+    uint64_t uid;          // never reused; batch tables key on it, not on the address
 };
+
+static uint64_t next_sim_uid() {
+    static uint64_t n = 0;
+    return ++n;
+}
 
 namespace {
 
@@ -356,7 +363,6 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     if (ns > (int64_t)1 << 31) return fail(FUGLBM_EINVAL, "grid too large");
     const int N = mix->N;
     // physical admissibility of the initial field (rho_i > 0, finite, b_m rt < 1)
-    std::vector<double> rbar(N, 0.0);
     for (int64_t s = 0; s < ns; ++s) {
         double eta = 0.0;
         for (int i = 0; i < N; ++i) {
@@ -364,7 +370,6 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
             if (!std::isfinite(r) || !(r > 0.0))
                 return fail(FUGLBM_EUNPHYSICAL, "rho_i must be finite and > 0");
             eta += mix->b[i] * r / mix->M[i];
-            rbar[i] += r;
         }
         if (!(eta < 1.0)) return fail(FUGLBM_EUNPHYSICAL, "b_m * rt >= 1 (outside the EOS domain)");
     }
@@ -427,7 +432,6 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
         c.M[i] = mix->M[i];
         c.invM[i] = 1.0 / mix->M[i];
         c.sqk[i] = mix->sqk[i];
-        c.rhobar[i] = s->fp32 ? rbar[i] / (double)ns : 0.0;
         for (int j = 0; j < N; ++j) c.aij[i * FUG_MAXC + j] = mix->aij[i * FUG_MAXC + j];
     }
     fuglbm_status rc = FUGLBM_OK;
@@ -466,6 +470,7 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     s->snap_step = 0;
     s->have_snap = false;
     s->sticky = 0;
+    s->uid = next_sim_uid();
     *out = s;
     return FUGLBM_OK;
 }
@@ -480,7 +485,6 @@ fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     int r = s->rows;
     if (s->lattice == FUGLBM_D2Q9) {
         r = rows == 0 ? auto_rows(s->nx, s->ny, s->N, s->fp32) : std::min<int>(rows, s->ny);
-        if (r < std::min(8, s->ny)) return fail(FUGLBM_EINVAL, "rows must be >= 8 (or the grid height)");
     }
     HIP_TRY(hipStreamSynchronize(s->last_stream));
     s->kernel = k;
@@ -499,7 +503,9 @@ fuglbm_status fuglbm_sim_info(const fuglbm_sim *s, int32_t *Q, int32_t *D, int64
     if (Q) *Q = s->Q;
     if (D) *D = s->D;
     if (sites) *sites = s->ns;
-    if (alg_bytes) *alg_bytes = 2 * (int64_t)s->Q * s->N * (s->fp32 ? 4 : 8) * s->ns;
+    if (alg_bytes)
+        *alg_bytes = 2 * (s->fp32 ? pop_buffer_bytes<float>(s->N, s->Q, s->ns)
+                                  : pop_buffer_bytes<double>(s->N, s->Q, s->ns));
     if (kernel) *kernel = s->kernel;
     return FUGLBM_OK;
 }
@@ -595,14 +601,24 @@ fuglbm_status fuglbm_read_populations(fuglbm_sim *s, double *g_out) {
     HIP_TRY(hipStreamSynchronize(s->last_stream));
     const size_t n = (size_t)s->N * s->Q * s->ns;
     if (s->fp32) {
-        std::vector<float> tmp(n);
-        HIP_TRY(hipMemcpy(tmp.data(), s->buf[s->parity], n * 4, hipMemcpyDeviceToHost));
-        for (size_t k = 0; k < n; ++k) g_out[k] = (double)tmp[k];
+        const int N = s->N, Q = s->Q;
+        const int64_t ns = s->ns;
+        std::vector<char> tmp((size_t)pop_buffer_bytes<float>(N, Q, ns));
+        HIP_TRY(hipMemcpy(tmp.data(), s->buf[s->parity], tmp.size(), hipMemcpyDeviceToHost));
+        const double *rest = (const double *)tmp.data();
+        const float *mov = (const float *)tmp.data();
+        for (int i = 0; i < N; ++i)
+            for (int a = 0; a < Q; ++a) {
+                double *o = g_out + ((size_t)i * Q + a) * ns;
+                if (a == 0)
+                    for (int64_t t = 0; t < ns; ++t) o[t] = rest[rest_offset<float>(Q, ns, i) + t];
+                else
+                    for (int64_t t = 0; t < ns; ++t)
+                        o[t] = (double)mov[move_offset<float>(N, Q, ns, i, a) + t];
+            }
     } else {
         HIP_TRY(hipMemcpy(g_out, s->buf[s->parity], n * 8, hipMemcpyDeviceToHost));
     }
-    for (int i = 0; i < s->N; ++i)
-        for (int64_t t = 0; t < s->ns; ++t) g_out[(size_t)i * s->Q * s->ns + t] += s->hc.rhobar[i];
     return FUGLBM_OK;
 }
 
@@ -612,14 +628,21 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *s, const double *g_in, int64_
     HIP_TRY(hipStreamSynchronize(s->last_stream));
     const size_t n = (size_t)s->N * s->Q * s->ns;
     if (s->fp32) {
-        std::vector<float> tmp(n);
-        for (size_t k = 0; k < n; ++k) tmp[k] = (float)g_in[k];
-        for (int i = 0; i < s->N; ++i)
-            for (int64_t t = 0; t < s->ns; ++t) {
-                const size_t k = (size_t)i * s->Q * s->ns + t;
-                tmp[k] = (float)(g_in[k] - s->hc.rhobar[i]);
+        const int N = s->N, Q = s->Q;
+        const int64_t ns = s->ns;
+        std::vector<char> tmp((size_t)pop_buffer_bytes<float>(N, Q, ns));
+        double *rest = (double *)tmp.data();
+        float *mov = (float *)tmp.data();
+        for (int i = 0; i < N; ++i)
+            for (int a = 0; a < Q; ++a) {
+                const double *g = g_in + ((size_t)i * Q + a) * ns;
+                if (a == 0)
+                    for (int64_t t = 0; t < ns; ++t) rest[rest_offset<float>(Q, ns, i) + t] = g[t];
+                else
+                    for (int64_t t = 0; t < ns; ++t)
+                        mov[move_offset<float>(N, Q, ns, i, a) + t] = (float)g[t];
             }
-        HIP_TRY(hipMemcpy(s->buf[0], tmp.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->buf[0], tmp.data(), tmp.size(), hipMemcpyHostToDevice));
     } else {
         HIP_TRY(hipMemcpy(s->buf[0], g_in, n * 8, hipMemcpyHostToDevice));
     }
@@ -635,20 +658,25 @@ fuglbm_status fuglbm_poke_population(fuglbm_sim *s, int32_t comp, int32_t a, int
     if (comp < 0 || comp >= s->N || a < 0 || a >= s->Q || site < 0 || site >= s->ns)
         return fail(FUGLBM_EINVAL, "index out of range");
     HIP_TRY(hipStreamSynchronize(s->last_stream));
-    const size_t k = ((size_t)comp * s->Q + a) * s->ns + site;
-    const double v = a == 0 ? value - s->hc.rhobar[comp] : value;
-    if (s->fp32) {
-        const float f = (float)v;
+    if (s->fp32 && a > 0) {
+        const float f = (float)value;
+        const int64_t k = move_offset<float>(s->N, s->Q, s->ns, comp, a) + site;
         HIP_TRY(hipMemcpy((float *)s->buf[s->parity] + k, &f, 4, hipMemcpyHostToDevice));
     } else {
-        HIP_TRY(hipMemcpy((double *)s->buf[s->parity] + k, &v, 8, hipMemcpyHostToDevice));
+        const int64_t k = (s->fp32 ? rest_offset<float>(s->Q, s->ns, comp)
+                                   : rest_offset<double>(s->Q, s->ns, comp) + (int64_t)a * s->ns) +
+                          site;
+        HIP_TRY(hipMemcpy((double *)s->buf[s->parity] + k, &value, 8, hipMemcpyHostToDevice));
     }
     return FUGLBM_OK;
 }
 
+void forget_sim_in_batches(const fuglbm_sim *s);
+
 void fuglbm_destroy_sim(fuglbm_sim *s) {
     if (!s) return;
     hipStreamSynchronize(s->last_stream);
+    forget_sim_in_batches(s);
     drop_graph(s);
     if (s->owned) hipFree(s->base);
     delete s;
@@ -666,12 +694,38 @@ namespace {
 
 struct BatchTable {
     std::vector<fuglbm_sim *> sims;
+    std::vector<uint64_t> uids;
     std::vector<int> parity0;
     FusedSim *dsims = nullptr;
     FusedItem *ditems = nullptr;
     size_t cap_sims = 0, cap_items = 0;
     int nitems = 0;
+    hipGraphExec_t graph = nullptr;   // GRAPH_STEPS launches starting at flip 0
 };
+
+fuglbm_status batch_graph(BatchTable &bt, int ncomp, bool fp32) {
+    if (bt.graph) return FUGLBM_OK;
+    hipStream_t cs = capture_stream();
+    if (!cs) return fail(FUGLBM_EDEVICE, "cannot create capture stream");
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_STEPS; ++k) {
+        hipError_t e = launch_fused_d2q9(ncomp, fp32, bt.ditems, bt.nitems, bt.dsims, k & 1, cs);
+        if (e != hipSuccess) {
+            hipGraph_t g;
+            hipStreamEndCapture(cs, &g);
+            return hip_fail(e, "batch capture");
+        }
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(cs, &g));
+    hipError_t e = hipGraphInstantiate(&bt.graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        bt.graph = nullptr;
+        return hip_fail(e, "hipGraphInstantiate (batch)");
+    }
+    return FUGLBM_OK;
+}
 
 std::map<std::pair<int, int>, BatchTable> &batch_tables() {
     static std::map<std::pair<int, int>, BatchTable> t;
@@ -680,6 +734,10 @@ std::map<std::pair<int, int>, BatchTable> &batch_tables() {
 
 fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));  // the old table may still be read by queued launches
+    if (bt.graph) {
+        hipGraphExecDestroy(bt.graph);
+        bt.graph = nullptr;
+    }
     std::vector<FusedSim> hs;
     std::vector<FusedItem> logical;
     for (size_t k = 0; k < group.size(); ++k) {
@@ -720,12 +778,34 @@ fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group
                       hipMemcpyHostToDevice));
     bt.nitems = (int)items.size();
     bt.sims = group;
+    bt.uids.clear();
+    for (auto *sp : group) bt.uids.push_back(sp->uid);
     bt.parity0.clear();
     for (auto *s : group) bt.parity0.push_back(s->parity);
     return FUGLBM_OK;
 }
 
 }  // namespace
+
+// A destroyed simulation's buffers may be handed to someone else: drop every
+// cached table (and its captured graph) that still refers to it.
+void forget_sim_in_batches(const fuglbm_sim *s) {
+    for (auto &kv : batch_tables()) {
+        BatchTable &bt = kv.second;
+        for (size_t k = 0; k < bt.sims.size(); ++k) {
+            if (bt.sims[k] == s && bt.uids[k] == s->uid) {
+                if (bt.graph) {
+                    hipGraphExecDestroy(bt.graph);
+                    bt.graph = nullptr;
+                }
+                bt.sims.clear();
+                bt.uids.clear();
+                bt.parity0.clear();
+                break;
+            }
+        }
+    }
+}
 
 extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count, int64_t nsteps,
                                           void *hip_stream) {
@@ -752,7 +832,9 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
     for (auto &kv : groups) {
         auto &group = kv.second;
         BatchTable &bt = batch_tables()[kv.first];
-        bool same = bt.sims == group;
+        bool same = bt.sims.size() == group.size();
+        for (size_t k = 0; same && k < group.size(); ++k)
+            same = bt.sims[k] == group[k] && bt.uids[k] == group[k]->uid;
         int flip = 0;
         if (same) {
             flip = group[0]->parity ^ bt.parity0[0];
@@ -764,9 +846,26 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             if (rc != FUGLBM_OK) return rc;
             flip = 0;
         }
-        for (int64_t k = 0; k < nsteps; ++k) {
-            hipError_t e = launch_fused_d2q9(kv.first.first, kv.first.second != 0, bt.ditems,
-                                             bt.nitems, bt.dsims, flip, st);
+        const int nc = kv.first.first;
+        const bool f32 = kv.first.second != 0;
+        int64_t left = nsteps;
+        if (left >= 2 * GRAPH_STEPS && flip == 1) {
+            hipError_t e = launch_fused_d2q9(nc, f32, bt.ditems, bt.nitems, bt.dsims, flip, st);
+            if (e != hipSuccess) return hip_fail(e, "batched step launch");
+            flip = 0;
+            --left;
+        }
+        if (left >= GRAPH_STEPS && flip == 0) {
+            // replay a captured run of GRAPH_STEPS launches (even: parity returns)
+            fuglbm_status rc = batch_graph(bt, nc, f32);
+            if (rc != FUGLBM_OK) return rc;
+            while (left >= GRAPH_STEPS) {
+                HIP_TRY(hipGraphLaunch(bt.graph, st));
+                left -= GRAPH_STEPS;
+            }
+        }
+        for (; left > 0; --left) {
+            hipError_t e = launch_fused_d2q9(nc, f32, bt.ditems, bt.nitems, bt.dsims, flip, st);
             if (e != hipSuccess) return hip_fail(e, "batched step launch");
             flip ^= 1;
         }

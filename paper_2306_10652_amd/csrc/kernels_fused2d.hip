@@ -118,29 +118,41 @@ __device__ __forceinline__ double frcp(double x) {
     return fma(r, e, r);
 }
 
+// Populations of one component at one site: the rest one in FP64, the
+// moving ones (directions 1..8) in the storage type.
+template <typename ST>
+struct PopRow {
+    double r;
+    ST m[8];
+};
+
 template <int NC, typename ST>
 struct Fused {
     FusedLds<NC> &L;
     cptr<SimConst> C;
-    gptr<ST> src[9];
-    gmptr<ST> dst[9];
+    gptr<double> srcR;
+    gmptr<double> dstR;
+    gptr<ST> src[8];     // direction a at src[a - 1]
+    gmptr<ST> dst[8];
     int comp, lane, nx, ny, xc, xm, xp, y0, rows;
     int wm3, wm2, wm1, w0;   // wrapped row indices of rows r-3 .. r (uniform)
     bool outl;
-    double invM, bi, sqki, rb, RT, invRT, omega, fcoef;
+    double invM, bi, sqki, RT, invRT, omega, fcoef;
     uint32_t bad;
 
-    __device__ __forceinline__ void load_row(ST (&g)[9], int wrow) const {
+    __device__ __forceinline__ void load_row(PopRow<ST> &g, int wrow) const {
         const uint32_t off = (uint32_t)(wrow * nx + xc);
+        g.r = srcR[off];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) g[a] = src[a][off];
+        for (int a = 0; a < 8; ++a) g.m[a] = src[a][off];
     }
 
     // One lead row r.  gA = row r-2 (collided), gC = row r (loaded), gD =
     // row r+1 (prefetched here).  rh* = rho_i of rows r-3 .. r (rh0 written
     // here), ps* = psi_i of rows r-3 .. r-1 (psm1 written here), sv* = s of
     // rows r-2 .. r (sv0 written here), sn / so = Sraw_i of rows r / r-1.
-    __device__ __forceinline__ void body(int r, int rend, ST (&gA)[9], ST (&gC)[9], ST (&gD)[9],
+    __device__ __forceinline__ void body(int r, int rend, PopRow<ST> &gA, PopRow<ST> &gC,
+                                         PopRow<ST> &gD,
                                          double rhm3, double rhm2, double rhm1, double &rh0,
                                          double psm3, double psm2, double &psm1, double svm2,
                                          double svm1, double &sv0, double &sn, double so) {
@@ -156,9 +168,9 @@ struct Fused {
         // ---- phase 1: moments of row r; G_i of row y; mixture terms of row r-1
         {
             double v[9];
+            v[0] = gC.r;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) v[a] = (double)gC[a];
-            v[0] += rb;
+            for (int a = 1; a < 9; ++a) v[a] = (double)gC.m[a - 1];
             double rho = 0.0;
 #pragma unroll
             for (int a = 0; a < 9; ++a) rho += v[a];
@@ -282,23 +294,32 @@ struct Fused {
             const uint32_t row0 = (uint32_t)(wm2 * nx);
             const uint32_t rowp = (uint32_t)(wm1 * nx);
             if (outl) {
-                // rest population and the four opposite pairs, stored as they are formed
-                dst[0][row0 + xc] =
-                    (ST)(fma(omc, (double)gA[0] + rb,
-                             fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho)) - rb);
+                // the four opposite pairs, stored as they are formed; then the
+                // rest population, which in FP32 storage also takes the
+                // rounding error of the eight moving ones (mass stays exact
+                // to FP64 rounding)
+                double err = 0.0;
+                auto put = [&](gmptr<ST> p, uint32_t at, double v) {
+                    const ST t = (ST)v;
+                    if (sizeof(ST) == 4) err += (double)t - v;
+                    p[at] = t;
+                };
                 double tp, tm;
                 collide_pair(A, B, C9, C3, K1, ux, Fx, Gx, tp, tm);
-                dst[1][row0 + xp] = (ST)fma(omc, (double)gA[1], (1.0 / 9.0) * tp);
-                dst[3][row0 + xm] = (ST)fma(omc, (double)gA[3], (1.0 / 9.0) * tm);
+                put(dst[0], row0 + xp, fma(omc, (double)gA.m[0], (1.0 / 9.0) * tp));
+                put(dst[2], row0 + xm, fma(omc, (double)gA.m[2], (1.0 / 9.0) * tm));
                 collide_pair(A, B, C9, C3, K1, uy, Fy, Gy, tp, tm);
-                dst[2][rowp + xc] = (ST)fma(omc, (double)gA[2], (1.0 / 9.0) * tp);
-                dst[4][rowm + xc] = (ST)fma(omc, (double)gA[4], (1.0 / 9.0) * tm);
+                put(dst[1], rowp + xc, fma(omc, (double)gA.m[1], (1.0 / 9.0) * tp));
+                put(dst[3], rowm + xc, fma(omc, (double)gA.m[3], (1.0 / 9.0) * tm));
                 collide_pair(A, B, C9, C3, K2, ux + uy, Fx + Fy, Gx + Gy, tp, tm);
-                dst[5][rowp + xp] = (ST)fma(omc, (double)gA[5], (1.0 / 36.0) * tp);
-                dst[7][rowm + xm] = (ST)fma(omc, (double)gA[7], (1.0 / 36.0) * tm);
+                put(dst[4], rowp + xp, fma(omc, (double)gA.m[4], (1.0 / 36.0) * tp));
+                put(dst[6], rowm + xm, fma(omc, (double)gA.m[6], (1.0 / 36.0) * tm));
                 collide_pair(A, B, C9, C3, K2, uy - ux, Fy - Fx, Gy - Gx, tp, tm);
-                dst[6][rowp + xm] = (ST)fma(omc, (double)gA[6], (1.0 / 36.0) * tp);
-                dst[8][rowm + xp] = (ST)fma(omc, (double)gA[8], (1.0 / 36.0) * tm);
+                put(dst[5], rowp + xm, fma(omc, (double)gA.m[5], (1.0 / 36.0) * tp));
+                put(dst[7], rowm + xp, fma(omc, (double)gA.m[7], (1.0 / 36.0) * tm));
+                const double g0 =
+                    fma(omc, gA.r, fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho));
+                dstR[row0 + xc] = sizeof(ST) == 4 ? g0 - err : g0;
             }
         }
     }
@@ -321,12 +342,16 @@ __global__ __launch_bounds__(64 * NC) void k_fused_d2q9(const FusedItem *__restr
     f.nx = C->nx;
     f.ny = C->ny;
     const int64_t ns = C->nsites;
-    const ST *bsrc = (const ST *)(par ? sm->buf[1] : sm->buf[0]);
-    ST *bdst = (ST *)(par ? sm->buf[0] : sm->buf[1]);
+    const char *bsrc = (const char *)(par ? sm->buf[1] : sm->buf[0]);
+    char *bdst = (char *)(par ? sm->buf[0] : sm->buf[1]);
+    const int64_t ro = rest_offset<ST>(9, ns, f.comp);
+    f.srcR = (gptr<double>)((const double *)bsrc + ro);
+    f.dstR = (gmptr<double>)((double *)bdst + ro);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        f.src[a] = (gptr<ST>)(bsrc + ((int64_t)f.comp * 9 + a) * ns);
-        f.dst[a] = (gmptr<ST>)(bdst + ((int64_t)f.comp * 9 + a) * ns);
+    for (int a = 1; a < 9; ++a) {
+        const int64_t mo = move_offset<ST>(NC, 9, ns, f.comp, a);
+        f.src[a - 1] = (gptr<ST>)((const ST *)bsrc + mo);
+        f.dst[a - 1] = (gmptr<ST>)((ST *)bdst + mo);
     }
     int xc = (it.x0 - 2 + f.lane) % f.nx;
     if (xc < 0) xc += f.nx;
@@ -339,7 +364,6 @@ __global__ __launch_bounds__(64 * NC) void k_fused_d2q9(const FusedItem *__restr
     f.invM = C->invM[f.comp];
     f.bi = C->b[f.comp];
     f.sqki = C->sqk[f.comp];
-    f.rb = C->rhobar[f.comp];
     f.RT = C->RT;
     f.invRT = 1.0 / C->RT;
     f.omega = C->omega;
@@ -353,9 +377,10 @@ __global__ __launch_bounds__(64 * NC) void k_fused_d2q9(const FusedItem *__restr
         f.wm1 = f.wm2 = f.wm3 = 0;
     }
 
-    ST g0[9], g1[9], g2[9], g3[9];
+    PopRow<ST> g0, g1, g2, g3;
+    g0.r = g1.r = g3.r = 0.0;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) g0[a] = g1[a] = g3[a] = (ST)0;
+    for (int a = 0; a < 8; ++a) g0.m[a] = g1.m[a] = g3.m[a] = (ST)0;
     f.load_row(g2, f.w0);
     // register rings: g0..g3 = populations of rows r-2 .. r+1; h = rho_i of
     // rows r-3 .. r; p = psi_i of rows r-3 .. r-1; s = s of rows r-2 .. r;
@@ -367,13 +392,20 @@ __global__ __launch_bounds__(64 * NC) void k_fused_d2q9(const FusedItem *__restr
     double qn = 0.0, qo = 0.0;
     for (int r = rbeg; r <= rend; ++r) {
         f.body(r, rend, g0, g2, g3, h1, h2, h3, h0, p1, p2, p3, s1, s2, s0, qn, qo);
+        {
+            const double t = g0.r;
+            g0.r = g1.r;
+            g1.r = g2.r;
+            g2.r = g3.r;
+            g3.r = t;
+        }
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const ST t = g0[a];
-            g0[a] = g1[a];
-            g1[a] = g2[a];
-            g2[a] = g3[a];
-            g3[a] = t;
+        for (int a = 0; a < 8; ++a) {
+            const ST t = g0.m[a];
+            g0.m[a] = g1.m[a];
+            g1.m[a] = g2.m[a];
+            g2.m[a] = g3.m[a];
+            g3.m[a] = t;
         }
         h1 = h2;
         h2 = h3;

@@ -1,4 +1,5 @@
-// Three-pass step for any lattice (D2Q9, D3Q19), FP64 or FP32 storage:
+// Three-pass step for any lattice (D2Q9, D3Q19), FP64 or FP32 storage
+// (population layouts: rest_offset / move_offset of the common header):
 //   pass 1  moments + local PR fugacity: rho_i, RT ln f_i, s = sum sqrt(kappa_j) rt_j, j
 //   pass 2  psi_i = RT ln f_i - sqrt(kappa_i) lap(s)             (Eq. (4)-(5))
 //   pass 3  F_i = -rt_i grad psi_i, G_i = grad rho_i, u, collide (Eq. (1)), push
@@ -50,22 +51,21 @@ __device__ __forceinline__ void lattice_grad(const int64_t *nb, Fn f, double &gx
 template <class L, typename ST>
 __global__ __launch_bounds__(TPB) void k_init(const SimConst *__restrict__ c,
                                               const double *__restrict__ rho,
-                                              ST *__restrict__ g) {
+                                              void *__restrict__ g) {
     const int64_t ns = c->nsites;
     const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (s >= ns) return;
     const int N = c->N;
     for (int i = 0; i < N; ++i) {
-        const double r = rho[(int64_t)i * ns + s];
-        st_pop(g + ((int64_t)i * L::Q) * ns + s, r - c->rhobar[i]);
+        ((double *)g)[rest_offset<ST>(L::Q, ns, i) + s] = rho[(int64_t)i * ns + s];
 #pragma unroll
-        for (int a = 1; a < L::Q; ++a) st_pop(g + ((int64_t)i * L::Q + a) * ns + s, 0.0);
+        for (int a = 1; a < L::Q; ++a) ((ST *)g)[move_offset<ST>(N, L::Q, ns, i, a) + s] = (ST)0;
     }
 }
 
 template <class L, typename ST>
 __global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict__ c,
-                                                     const ST *__restrict__ g,
+                                                     const void *__restrict__ g,
                                                      double *__restrict__ rho_f,
                                                      double *__restrict__ psi_f,
                                                      double *__restrict__ s_f,
@@ -86,8 +86,7 @@ __global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict_
             double r = 0.0;
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) {
-                double v = ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
-                if (a == 0) v += c->rhobar[i];
+                const double v = ld_pop<ST>(g, N, L::Q, ns, i, a, s);
                 r += v;
                 jx += L::ex(a) * v;
                 jy += L::ey(a) * v;
@@ -181,7 +180,7 @@ __device__ __forceinline__ void site_velocity(const SimConst *c, int64_t s, cons
 
 template <class L, typename ST>
 __global__ __launch_bounds__(TPB) void k_collide(const SimConst *__restrict__ c,
-                                                 const ST *__restrict__ gs, ST *__restrict__ gd,
+                                                 const void *__restrict__ gs, void *__restrict__ gd,
                                                  const double *__restrict__ rho_f,
                                                  const double *__restrict__ psi_f,
                                                  const double *__restrict__ j_f) {
@@ -209,16 +208,22 @@ __global__ __launch_bounds__(TPB) void k_collide(const SimConst *__restrict__ c,
         const double Fx = -rt * gx, Fy = -rt * gy, Fz = -rt * gz;
         const double Fu = Fx * ux + Fy * uy + Fz * uz;
         const double Gu = Gx * ux + Gy * uy + Gz * uz;
-        const double rb = c->rhobar[i];
+        // moving populations first; in FP32 storage their rounding error
+        // goes into the rest population, which stays at this site
+        double err = 0.0;
 #pragma unroll
-        for (int a = 0; a < L::Q; ++a) {
-            double gv = ld_pop(gs + ((int64_t)i * L::Q + a) * ns + s);
-            if (a == 0) gv += rb;
-            double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
-                                      omega, fcoef);
-            if (a == 0) o -= rb;
-            st_pop(gd + ((int64_t)i * L::Q + a) * ns + nb[a], o);
+        for (int a = 1; a < L::Q; ++a) {
+            const double gv = ld_pop<ST>(gs, N, L::Q, ns, i, a, s);
+            const double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu,
+                                            Gu, omega, fcoef);
+            const ST v = (ST)o;
+            if (sizeof(ST) == 4) err += (double)v - o;
+            ((ST *)gd)[move_offset<ST>(N, L::Q, ns, i, a) + nb[a]] = v;
         }
+        const double g0 = ld_pop<ST>(gs, N, L::Q, ns, i, 0, s);
+        const double o0 = collide_one<L>(0, g0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
+                                         omega, fcoef);
+        ((double *)gd)[rest_offset<ST>(L::Q, ns, i) + s] = sizeof(ST) == 4 ? o0 - err : o0;
     }
 }
 
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(TPB) void k_velocity(const SimConst *__restrict__ c
 // part[b][0..N) mass, [N..2N) sum |rho_i - snap_i|, [2N..2N+3) momentum.
 template <class L, typename ST>
 __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
-                                              const ST *__restrict__ g,
+                                              const void *__restrict__ g,
                                               double *__restrict__ snap,
                                               double *__restrict__ part, int use_snap) {
     __shared__ double red[TPB];
@@ -268,13 +273,12 @@ __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
                 double r = 0.0;
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) {
-                    const double v = ld_pop(g + ((int64_t)i * L::Q + a) * ns + s);
+                    const double v = ld_pop<ST>(g, N, L::Q, ns, i, a, s);
                     r += v;
                     mom[0] += L::ex(a) * v;
                     mom[1] += L::ey(a) * v;
                     mom[2] += L::ez(a) * v;
                 }
-                r += c->rhobar[i];
                 mass[i] += r;
                 double *sp = snap + (int64_t)i * ns + s;
                 if (use_snap) res[i] += fabs(r - *sp);
@@ -286,8 +290,8 @@ __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
         double v = 0.0;
 #pragma unroll
         for (int i = 0; i < FUG_MAXC; ++i) {
-            if (q == i) v = mass[i];
-            if (q == N + i) v = res[i];
+            if (i < N && q == i) v = mass[i];
+            if (i < N && q == N + i) v = res[i];
         }
         if (q >= 2 * N) v = mom[q - 2 * N];
         red[threadIdx.x] = v;
@@ -308,11 +312,11 @@ hipError_t step_generic_t(const SimConst *c, int64_t ns, const void *gs, void *g
                           double *psi_f, double *s_f, double *j_f, uint32_t *status,
                           hipStream_t st) {
     const unsigned nb = nblocks(ns);
-    hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, (const ST *)gs,
-                       rho_f, psi_f, s_f, j_f, status);
+    hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, gs, rho_f, psi_f,
+                       s_f, j_f, status);
     hipLaunchKernelGGL((k_interface<L>), dim3(nb), dim3(TPB), 0, st, c, s_f, psi_f);
-    hipLaunchKernelGGL((k_collide<L, ST>), dim3(nb), dim3(TPB), 0, st, c, (const ST *)gs,
-                       (ST *)gd, rho_f, psi_f, j_f);
+    hipLaunchKernelGGL((k_collide<L, ST>), dim3(nb), dim3(TPB), 0, st, c, gs, gd, rho_f, psi_f,
+                       j_f);
     return hipGetLastError();
 }
 
@@ -321,8 +325,8 @@ hipError_t fields_generic_t(const SimConst *c, int64_t ns, const void *g, double
                             double *psi_f, double *s_f, double *j_f, double *u_f,
                             uint32_t *status, hipStream_t st) {
     const unsigned nb = nblocks(ns);
-    hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, (const ST *)g,
-                       rho_f, psi_f, s_f, j_f, status);
+    hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, g, rho_f, psi_f,
+                       s_f, j_f, status);
     hipLaunchKernelGGL((k_interface<L>), dim3(nb), dim3(TPB), 0, st, c, s_f, psi_f);
     if (u_f)
         hipLaunchKernelGGL((k_velocity<L>), dim3(nb), dim3(TPB), 0, st, c, rho_f, psi_f, j_f,
@@ -336,11 +340,11 @@ hipError_t launch_init(int lattice, bool fp32, const SimConst *c, int64_t ns, co
                        void *g, hipStream_t st) {
     const unsigned nb = nblocks(ns);
     if (lattice == 0) {
-        if (fp32) hipLaunchKernelGGL((k_init<D2Q9, float>), dim3(nb), dim3(TPB), 0, st, c, rho, (float *)g);
-        else hipLaunchKernelGGL((k_init<D2Q9, double>), dim3(nb), dim3(TPB), 0, st, c, rho, (double *)g);
+        if (fp32) hipLaunchKernelGGL((k_init<D2Q9, float>), dim3(nb), dim3(TPB), 0, st, c, rho, g);
+        else hipLaunchKernelGGL((k_init<D2Q9, double>), dim3(nb), dim3(TPB), 0, st, c, rho, g);
     } else {
-        if (fp32) hipLaunchKernelGGL((k_init<D3Q19, float>), dim3(nb), dim3(TPB), 0, st, c, rho, (float *)g);
-        else hipLaunchKernelGGL((k_init<D3Q19, double>), dim3(nb), dim3(TPB), 0, st, c, rho, (double *)g);
+        if (fp32) hipLaunchKernelGGL((k_init<D3Q19, float>), dim3(nb), dim3(TPB), 0, st, c, rho, g);
+        else hipLaunchKernelGGL((k_init<D3Q19, double>), dim3(nb), dim3(TPB), 0, st, c, rho, g);
     }
     return hipGetLastError();
 }
@@ -368,11 +372,11 @@ hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, 
 hipError_t launch_diag(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
                        double *snap, double *part, int nblk, int use_snap, hipStream_t st) {
     if (lattice == 0) {
-        if (fp32) hipLaunchKernelGGL((k_diag<D2Q9, float>), dim3(nblk), dim3(TPB), 0, st, c, (const float *)g, snap, part, use_snap);
-        else hipLaunchKernelGGL((k_diag<D2Q9, double>), dim3(nblk), dim3(TPB), 0, st, c, (const double *)g, snap, part, use_snap);
+        if (fp32) hipLaunchKernelGGL((k_diag<D2Q9, float>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
+        else hipLaunchKernelGGL((k_diag<D2Q9, double>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
     } else {
-        if (fp32) hipLaunchKernelGGL((k_diag<D3Q19, float>), dim3(nblk), dim3(TPB), 0, st, c, (const float *)g, snap, part, use_snap);
-        else hipLaunchKernelGGL((k_diag<D3Q19, double>), dim3(nblk), dim3(TPB), 0, st, c, (const double *)g, snap, part, use_snap);
+        if (fp32) hipLaunchKernelGGL((k_diag<D3Q19, float>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
+        else hipLaunchKernelGGL((k_diag<D3Q19, double>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
     }
     return hipGetLastError();
 }

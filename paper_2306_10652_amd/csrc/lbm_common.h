@@ -28,7 +28,6 @@ struct SimConst {
     double M[FUG_MAXC];
     double invM[FUG_MAXC];
     double sqk[FUG_MAXC];     // sqrt(kappa_i)
-    double rhobar[FUG_MAXC];  // FP32-storage offset of the rest population
     double aij[FUG_MAXC * FUG_MAXC];  // (a alpha)_ij, row-major, stride FUG_MAXC
 };
 
@@ -142,8 +141,30 @@ __device__ __forceinline__ double collide_one(int a, double g, double rho, doubl
     return g - omega * (g - geq) + fcoef * Fa;
 }
 
-// Storage conversion (FP64 or FP32 deviation storage).
-__device__ __forceinline__ double ld_pop(const double *p) { return *p; }
-__device__ __forceinline__ double ld_pop(const float *p) { return (double)*p; }
-__device__ __forceinline__ void st_pop(double *p, double v) { *p = v; }
-__device__ __forceinline__ void st_pop(float *p, double v) { *p = (float)v; }
+// Population storage of one buffer, component-major structure of arrays.
+//   FP64 (ST = double):   g[i][a][site], a = 0 .. Q-1, all doubles.
+//   FP32 storage (float): the rest populations g[i][0][site] of all
+//     components as doubles, then the moving ones g[i][a][site],
+//     a = 1 .. Q-1, as floats.  A kernel that writes a site folds the
+//     rounding error of the site's moving populations into its rest
+//     population, so every component's mass is conserved to FP64 rounding.
+template <typename ST>
+__host__ __device__ __forceinline__ int64_t rest_offset(int Q, int64_t ns, int i) {
+    return (int64_t)i * (sizeof(ST) == 8 ? Q : 1) * ns;          // in doubles
+}
+template <typename ST>
+__host__ __device__ __forceinline__ int64_t move_offset(int N, int Q, int64_t ns, int i, int a) {
+    return sizeof(ST) == 8 ? ((int64_t)i * Q + a) * ns                       // in doubles
+                           : 2 * (int64_t)N * ns + ((int64_t)i * (Q - 1) + a - 1) * ns;  // floats
+}
+template <typename ST>
+__host__ __device__ __forceinline__ int64_t pop_buffer_bytes(int N, int Q, int64_t ns) {
+    return (int64_t)N * ns * 8 + (int64_t)N * (Q - 1) * ns * (int64_t)sizeof(ST);
+}
+
+template <typename ST>
+__device__ __forceinline__ double ld_pop(const void *buf, int N, int Q, int64_t ns, int i, int a,
+                                         int64_t s) {
+    if (a == 0) return ((const double *)buf)[rest_offset<ST>(Q, ns, i) + s];
+    return (double)((const ST *)buf)[move_offset<ST>(N, Q, ns, i, a) + s];
+}

@@ -1,0 +1,194 @@
+"""Continuous-batching simulation server.
+
+Requests (a mixture, a lattice and grid, an initial field) arrive over time.
+A request is admitted as soon as its device memory fits the HBM budget and
+a slot is free; from then on it shares the GPU with every other admitted
+request: each tick advances all active D2Q9 simulations with one batched
+launch per step (``fuglbm_step_many``, grouped by component count) and the
+D3Q19 ones with their own launches, all on one stream, then reads every
+simulation's residual (``fuglbm_diagnostics``).  A simulation retires when
+its residual R_K <= tol (K = steps per tick) or at its step cap; its fields
+are read back and its memory returned, and waiting requests are admitted.
+
+Latency = finish - arrival, service = finish - admit, both wall clock.
+"""
+import heapq
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import capi
+
+
+@dataclass
+class Request:
+    rid: int
+    comps: list
+    T: float
+    lattice: int
+    shape: tuple
+    rho: np.ndarray
+    arrival: float = 0.0            # seconds after the server starts
+    kij: object = None
+    precision: int = capi.FP32_STORAGE
+    tol: float = 1e-8
+    max_steps: int = 200000
+    # filled by the server
+    admit_t: float = None
+    finish_t: float = None
+    steps: int = 0
+    residual: float = None
+    converged: bool = False
+    status: int = 0
+    result: dict = field(default=None, repr=False)
+
+    @property
+    def N(self):
+        return len(self.comps)
+
+    def nbytes(self):
+        nx, ny, nz = (tuple(self.shape) + (1, 1))[:3]
+        return capi.fields_bytes(self.N, self.lattice, self.precision, nx, ny, nz)
+
+    def csu(self):
+        return int(np.prod(self.shape)) * self.N * self.steps
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes, chunk=200, max_active=64, kappa_ref=0.02,
+                 keep_fields=False, stream=None):
+        import torch
+        self.budget = int(hbm_budget_bytes)
+        self.chunk = int(chunk)
+        self.max_active = int(max_active)
+        self.kappa_ref = kappa_ref
+        self.keep_fields = keep_fields
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.used = 0
+        self.done = []
+
+    # -- lifecycle of one request --------------------------------------
+    def _admit(self, req, now):
+        mix = capi.Mixture.from_components(req.comps, req.T, req.kij, kappa_ref=self.kappa_ref)
+        sim = capi.Simulation(mix, req.lattice, req.precision, req.shape, req.rho,
+                              stream=self.stream)
+        sim.diagnostics()                  # snapshot for the first residual
+        req.admit_t = now
+        self.used += req.nbytes()
+        return dict(req=req, mix=mix, sim=sim)
+
+    def _retire(self, slot, now, status=0):
+        req, sim = slot["req"], slot["sim"]
+        if self.keep_fields and status == 0:
+            req.result = dict(populations=sim.read_populations(),
+                              rho=sim.read_moments(velocity=False)["rho"])
+        req.finish_t = now
+        req.status = status
+        sim.close()
+        slot["mix"].close()
+        self.used -= req.nbytes()
+        self.done.append(req)
+
+    def run(self, requests, clock=time.perf_counter):
+        """Serve `requests` (their `arrival` offsets are honoured in wall
+        clock) until all are finished.  Returns the finished requests."""
+        pending = [(r.arrival, r.rid, r) for r in requests]
+        heapq.heapify(pending)
+        waiting = []          # arrived, not admitted (FIFO)
+        active = []
+        t0 = clock()
+        while pending or waiting or active:
+            now = clock() - t0
+            while pending and pending[0][0] <= now:
+                waiting.append(heapq.heappop(pending)[2])
+            # admission: FIFO, by HBM budget and slots
+            while waiting and len(active) < self.max_active:
+                req = waiting[0]
+                if req.nbytes() > self.budget:
+                    waiting.pop(0)
+                    req.status = -1               # can never fit
+                    req.finish_t = now
+                    self.done.append(req)
+                    continue
+                if self.used + req.nbytes() > self.budget:
+                    break
+                waiting.pop(0)
+                try:
+                    active.append(self._admit(req, clock() - t0))
+                except capi.FuglbmError as e:      # rejected input: fails alone
+                    req.status = e.status
+                    req.finish_t = clock() - t0
+                    self.done.append(req)
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(0.05, pending[0][0] - (clock() - t0))))
+                continue
+            # one tick: every active simulation advances `chunk` steps
+            d2 = [s for s in active if s["req"].lattice == capi.D2Q9]
+            d3 = [s for s in active if s["req"].lattice != capi.D2Q9]
+            if d2:
+                rc = capi.fuglbm_step_many([s["sim"] for s in d2], self.chunk, self.stream)
+                if rc not in (0, 5):
+                    capi.check(rc)
+            for s in d3:
+                try:
+                    s["sim"].step_n(self.chunk)
+                except capi.FuglbmError:
+                    pass
+            still = []
+            for s in active:
+                req = s["req"]
+                d = s["sim"].diagnostics()
+                req.steps = d["step"]
+                req.residual = d["residual"]
+                if d["rc"] != 0:
+                    self._retire(s, clock() - t0, status=d["rc"])
+                elif req.residual <= req.tol:
+                    req.converged = True
+                    self._retire(s, clock() - t0)
+                elif req.steps >= req.max_steps:
+                    self._retire(s, clock() - t0)
+                else:
+                    still.append(s)
+            active = still
+        return self.done
+
+
+def latency_stats(done):
+    lat = np.array([r.finish_t - r.arrival for r in done if r.status == 0])
+    svc = np.array([r.finish_t - r.admit_t for r in done if r.status == 0])
+    if lat.size == 0:
+        return dict(n=0)
+    return dict(n=int(lat.size), p50_s=float(np.percentile(lat, 50)),
+                p99_s=float(np.percentile(lat, 99)), service_p50_s=float(np.percentile(svc, 50)),
+                service_p99_s=float(np.percentile(svc, 99)),
+                converged=int(sum(r.converged for r in done)))
+
+
+def pool_requests(states, count, rate_hz, seed=5, precision=capi.FP32_STORAGE, tol=1e-8,
+                  max_steps=200000, max_n2d=None, max_n3d=None):
+    """Requests from the stored serving pool, Poisson arrivals at `rate_hz`."""
+    from inputs import fields as Fi
+    from .batch import _Comp
+    comps_all = [_Comp(**c) for c in states["components"]]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for k, q in enumerate(states["requests"][:count]):
+        t += rng.exponential(1.0 / rate_hz)
+        N = q["N"]
+        n = q["n"]
+        if q["lattice"] == "D2Q9":
+            if max_n2d:
+                n = min(n, max_n2d)
+            rho = Fi.slab(n, n, q["rho_V"], q["rho_L"], q["S_V"])
+            lat, shape = capi.D2Q9, (n, n)
+        else:
+            if max_n3d:
+                n = min(n, max_n3d)
+            rho = Fi.slab(n, n, q["rho_V"], q["rho_L"], q["S_V"], nz=n)
+            lat, shape = capi.D3Q19, (n, n, n)
+        out.append(Request(k, comps_all[:N], q["T"], lat, shape, rho, arrival=t,
+                           precision=precision, tol=tol, max_steps=max_steps))
+    return out

@@ -76,6 +76,8 @@ def test_fields_bytes():
     b64 = L.fuglbm_fields_bytes(10, capi.D2Q9, capi.FP64, 1024, 1024, 1)
     b32 = L.fuglbm_fields_bytes(10, capi.D2Q9, capi.FP32_STORAGE, 1024, 1024, 1)
     pop64 = 2 * 9 * 10 * 8 * 1024 * 1024
-    assert b64 >= pop64 and b64 - b32 == pop64 // 2
+    # FP32 storage: rest populations FP64, the 8 moving ones FP32
+    pop32 = 2 * (8 + 8 * 4) * 10 * 1024 * 1024
+    assert b64 >= pop64 and b64 - b32 == pop64 - pop32
     assert L.fuglbm_fields_bytes(0, 0, 0, 8, 8, 1) == 0
     assert L.fuglbm_fields_bytes(3, 1, 0, 8, 8, 8) >= 2 * 19 * 3 * 8 * 512

@@ -1,0 +1,151 @@
+"""Batched sweeps and the continuous-batching server (GPU).
+
+* A batched step (one launch for many uneven simulations, hipGraph-replayed)
+  gives bitwise the same populations as stepping each simulation alone.
+* FP32 storage against FP64 on the same batch: bulk phase densities within
+  1e-4 relative and mole fractions within 1e-3 absolute.
+* The server: every request's result is bitwise the same alone and in the
+  mix; the HBM budget is never exceeded; a request that goes non-finite
+  fails alone while the others finish normally.
+"""
+import numpy as np
+import pytest
+
+from tests import workloads as W
+from tests.test_gpu_parity import _capi, report
+
+pytestmark = pytest.mark.gpu
+
+
+def small_specs(count=8, max_n=96):
+    from paper_2306_10652_amd import batch
+    specs = batch.ternary_specs(W.states()["ternary_sweep"], count=count)
+    out = []
+    from inputs import fields as Fi
+    inst = W.states()["ternary_sweep"]["instances"]
+    for sp, st in zip(specs, inst):
+        n = min(st["n"], max_n) - (7 if len(out) % 2 else 0)   # uneven, ragged grids
+        sp = dict(sp)
+        sp["shape"] = (n, n)
+        sp["rho"] = Fi.slab(n, n, st["rho_V"], st["rho_L"], st["S_V"])
+        out.append(sp)
+    return out
+
+
+def test_batched_equals_single_bitwise():
+    capi = _capi()
+    from paper_2306_10652_amd import batch
+    specs = small_specs()
+    sw = batch.Sweep(specs, capi.FP32_STORAGE)
+    sw.step(37)
+    sw.step(163)      # graph-replayed runs + a remainder
+    singles = batch.Sweep(specs, capi.FP32_STORAGE)
+    singles.step_sequential(200)
+    for a, b in zip(sw.sims, singles.sims):
+        assert np.array_equal(a.read_populations(), b.read_populations())
+    sw.close()
+    singles.close()
+
+
+def test_fp32_batch_against_fp64_equilibrium_phases():
+    """FP32 storage against FP64 at equilibrium (thin ternary slabs run to a
+    stationary state): bulk phase densities within 1e-4 relative and mole
+    fractions within 1e-3 absolute (bulk = even-width window averages)."""
+    capi = _capi()
+    from paper_2306_10652_amd import batch
+    from inputs import fields as Fi
+    specs = []
+    for sp, st in zip(batch.ternary_specs(W.states()["ternary_sweep"], count=6),
+                      W.states()["ternary_sweep"]["instances"]):
+        sp = dict(sp)
+        sp["shape"] = (64, 4)
+        sp["rho"] = Fi.slab(64, 4, st["rho_V"], st["rho_L"], 0.5)
+        specs.append(sp)
+    a = batch.Sweep(specs, capi.FP32_STORAGE)
+    b = batch.Sweep(specs, capi.FP64)
+    a.step(200000)
+    b.step(200000)
+    worst_rho, worst_x = 0.0, 0.0
+    for pa, pb in zip(a.phases(), b.phases()):
+        for ph in ("rho_V", "rho_L"):
+            worst_rho = max(worst_rho, abs(pa[ph] / pb[ph] - 1))
+        worst_x = max(worst_x, np.max(np.abs(pa["x"] - pb["x"])), np.max(np.abs(pa["y"] - pb["y"])))
+    report("fp32_vs_fp64_equilibrium", rho_rel=worst_rho, x_abs=worst_x)
+    assert worst_rho <= 1e-4 and worst_x <= 1e-3
+    a.close()
+    b.close()
+
+
+def serving_requests(count=5, tol=1e-6, max_steps=4000):
+    from paper_2306_10652_amd import serve
+    reqs = serve.pool_requests(W.states()["serving_pool"], count, rate_hz=200.0, tol=tol,
+                               max_steps=max_steps, max_n2d=96, max_n3d=20)
+    return reqs
+
+
+def test_server_alone_equals_mix_and_budget():
+    capi = _capi()
+    from paper_2306_10652_amd import serve
+    alone = {}
+    for r in serving_requests():
+        r.arrival = 0.0
+        srv = serve.Server(8 << 30, chunk=200, keep_fields=True)
+        srv.run([r])
+        alone[r.rid] = r
+    mix = serving_requests()
+    one = mix[0]
+    budget = one.nbytes() + max(r.nbytes() for r in mix[1:]) + 1   # at most ~2 resident
+    srv = serve.Server(budget, chunk=200, keep_fields=True)
+    peak = [0]
+    admit = srv._admit
+
+    def watch(req, now):
+        s = admit(req, now)
+        peak[0] = max(peak[0], srv.used)
+        return s
+    srv._admit = watch
+    done = srv.run(mix)
+    assert peak[0] <= budget
+    assert len(done) == len(mix)
+    for r in done:
+        a = alone[r.rid]
+        report("serve_mix", rid=r.rid, steps=r.steps, alone_steps=a.steps,
+               converged=r.converged, latency=r.finish_t - r.arrival)
+        assert r.status == 0 and r.steps == a.steps
+        assert np.array_equal(r.result["populations"], a.result["populations"])
+    st = serve.latency_stats(done)
+    assert st["n"] == len(mix) and st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_server_isolates_a_failing_request():
+    """A request whose state turns non-finite (a NaN written into one
+    population after admission) fails alone with ENONFINITE; the requests
+    sharing the batched launches with it finish exactly as they do alone."""
+    capi = _capi()
+    from paper_2306_10652_amd import serve
+    alone = {}
+    for r in serving_requests(count=3):
+        r.arrival = 0.0
+        srv = serve.Server(8 << 30, chunk=200, keep_fields=True)
+        srv.run([r])
+        alone[r.rid] = r
+    reqs = serving_requests(count=3)
+    bad = serving_requests(count=1)[0]
+    bad.rid = 99
+    srv = serve.Server(8 << 30, chunk=200, keep_fields=True)
+    admit = srv._admit
+
+    def poison(req, now):
+        slot = admit(req, now)
+        if req.rid == 99:
+            slot["sim"].poke(0, 0, 5, float("nan"))
+        return slot
+    srv._admit = poison
+    done = srv.run(reqs + [bad])
+    by = {r.rid: r for r in done}
+    report("serve_isolation", bad_status=by[99].status, others=[by[r.rid].steps for r in reqs])
+    assert by[99].status == 5
+    for r in reqs:
+        got = by[r.rid]
+        assert got.status == 0 and got.steps == alone[r.rid].steps
+        assert np.array_equal(got.result["populations"], alone[r.rid].result["populations"])

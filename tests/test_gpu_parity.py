@@ -59,7 +59,8 @@ def test_droplet64_2000_steps_fp64(kernel):
 
 @pytest.mark.parametrize("shape,N,rows", [((67, 45), 3, 8), ((61, 7), 2, 0), ((5, 5), 1, 0),
                                           ((1, 9), 2, 0), ((130, 2), 4, 0), ((64, 64), 16, 16),
-                                          ((200, 19), 10, 8)])
+                                          ((200, 19), 10, 8), ((67, 45), 3, 1),
+                                          ((61, 23), 5, 2), ((125, 17), 7, 3)])
 def test_ragged_grids_few_steps(shape, N, rows):
     """Ragged strips / chunks, degenerate widths (1, 2, 5), N = 1..16: fused
     kernel after 1 and 7 steps, populations and densities."""
@@ -96,7 +97,7 @@ def test_vle_cases_fp64(case):
 
 @pytest.mark.parametrize("case", [2, 6])
 def test_vle_fp32_storage(case):
-    """FP32 deviation storage vs the FP64 oracle after 500 steps: every
+    """FP32 storage vs the FP64 oracle after 500 steps: every
     density within the FP32-storage bar of 1e-4 relative."""
     wl = W.vle(case)
     o = wl.oracle()
