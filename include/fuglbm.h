@@ -159,7 +159,14 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int6
 
 /* Launch tuning: kernel 0 = automatic, 1 = three-pass generic kernels,
  * 2 = fused one-pass D2Q9 kernel; rows = output rows per fused work item
- * (0 = automatic).  EINVAL for a kernel the simulation cannot use. */
+ * (>= 1, fixed), or 0 = autotuned: the next fuglbm_step_n times a few
+ * trial launches per candidate (they read the current state and write the
+ * spare buffer, so the state does not move) and keeps the fastest; the
+ * choice is cached per (nx, ny, ncomp, precision) for the process.  The
+ * state does not depend on rows.  fuglbm_step_many tunes one rows value
+ * per batch shape the same way unless a member has fixed rows.
+ * Autotuning is the default.  EINVAL for a kernel the simulation cannot
+ * use, or rows < 0. */
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *sim, int32_t kernel, int32_t rows);
 
 /* Query: Q, spatial dimension, sites, bytes moved per step by the

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fuglbm.h"
@@ -150,6 +151,8 @@ struct fuglbm_sim {
     int nitems;
     int kernel;            // 1 generic, 2 fused
     int rows;
+    bool autotune;         // rows chosen by timing (not fixed by the caller)
+    bool tuned;            // autotune done (or answered from the cache)
     int64_t step;
     int64_t snap_step;
     bool have_snap;
@@ -242,6 +245,103 @@ fuglbm_status ensure_graph(fuglbm_sim *s) {
     s->graph.kernel = s->kernel;
     s->graph.rows = s->rows;
     return FUGLBM_OK;
+}
+
+// ---- rows-per-item autotuner ---------------------------------------------
+// Candidates are timed on trial launches that read the current state and
+// write the other buffer without swapping them: the state does not move,
+// and the next real step overwrites what the trials wrote.  (Every rows
+// value gives bitwise the same new state, since each site's arithmetic does
+// not depend on which work item computes it.)  The winner is cached per
+// (nx, ny, N, precision) for the process, and per batch shape for batched
+// launches.
+constexpr int TUNE_ROWS[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+constexpr int TUNE_LAUNCHES = 4;
+
+std::vector<int> tune_candidates(int ny, int model) {
+    std::vector<int> c;
+    for (int r : TUNE_ROWS)
+        if (r < ny) c.push_back(r);
+    c.push_back(ny);
+    if (model > 0 && model < ny) c.push_back(model);
+    std::sort(c.begin(), c.end());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
+    return c;
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer() {
+        if (hipEventCreate(&a) != hipSuccess) a = nullptr;
+        if (hipEventCreate(&b) != hipSuccess) b = nullptr;
+    }
+    ~Timer() {
+        if (a) hipEventDestroy(a);
+        if (b) hipEventDestroy(b);
+    }
+    bool ok() const { return a && b; }
+};
+
+// Times `launch` (TUNE_LAUNCHES back-to-back launches) after `prepare(r)`
+// for every candidate r; returns the fastest.
+template <class Prep, class Launch>
+fuglbm_status time_candidates(const std::vector<int> &cand, hipStream_t st, Prep prepare,
+                              Launch launch, int &best) {
+    Timer tm;
+    if (!tm.ok()) return fail(FUGLBM_EDEVICE, "hipEventCreate");
+    float best_ms = 1e30f;
+    best = cand.empty() ? 0 : cand[0];
+    bool warm = false;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        fuglbm_status rc = prepare(cand[k]);
+        if (rc != FUGLBM_OK) return rc;
+        if (!warm) {   // first launch of the kernel: not timed
+            HIP_TRY(launch());
+            warm = true;
+        }
+        HIP_TRY(hipEventRecord(tm.a, st));
+        for (int j = 0; j < TUNE_LAUNCHES; ++j) HIP_TRY(launch());
+        HIP_TRY(hipEventRecord(tm.b, st));
+        HIP_TRY(hipEventSynchronize(tm.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, tm.a, tm.b));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[k];
+        }
+    }
+    return FUGLBM_OK;
+}
+
+std::map<std::tuple<int, int, int, int>, int> &tune_cache() {
+    static std::map<std::tuple<int, int, int, int>, int> m;
+    return m;
+}
+
+fuglbm_status set_rows(fuglbm_sim *s, int rows, hipStream_t st) {
+    if (rows == s->rows) return FUGLBM_OK;
+    HIP_TRY(hipStreamSynchronize(st));   // queued launches still read the item table
+    s->rows = rows;
+    return build_items(s);
+}
+
+fuglbm_status autotune_rows(fuglbm_sim *s, hipStream_t st) {
+    const auto key = std::make_tuple(s->nx, s->ny, s->N, s->fp32 ? 1 : 0);
+    auto hit = tune_cache().find(key);
+    int best = 0;
+    if (hit != tune_cache().end()) {
+        best = hit->second;
+    } else {
+        const std::vector<int> cand =
+            tune_candidates(s->ny, auto_rows(s->nx, s->ny, s->N, s->fp32));
+        fuglbm_status rc = time_candidates(
+            cand, st, [&](int r) { return set_rows(s, r, st); },
+            [&]() { return launch_one_step(s, s->parity, st); }, best);
+        if (rc != FUGLBM_OK) return rc;
+        tune_cache()[key] = best;
+    }
+    s->tuned = true;
+    return set_rows(s, best, st);
 }
 
 fuglbm_status sync_status(fuglbm_sim *s) {
@@ -470,6 +570,8 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     s->snap_step = 0;
     s->have_snap = false;
     s->sticky = 0;
+    s->autotune = lattice == FUGLBM_D2Q9;
+    s->tuned = false;
     s->uid = next_sim_uid();
     *out = s;
     return FUGLBM_OK;
@@ -485,6 +587,8 @@ fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     int r = s->rows;
     if (s->lattice == FUGLBM_D2Q9) {
         r = rows == 0 ? auto_rows(s->nx, s->ny, s->N, s->fp32) : std::min<int>(rows, s->ny);
+        s->autotune = rows == 0;
+        s->tuned = false;
     }
     HIP_TRY(hipStreamSynchronize(s->last_stream));
     s->kernel = k;
@@ -517,6 +621,10 @@ fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
     hipStream_t st = (hipStream_t)hip_stream;
     s->last_stream = st;
     int64_t left = nsteps;
+    if (left > 0 && s->kernel == 2 && s->autotune && !s->tuned) {
+        fuglbm_status rc = autotune_rows(s, st);
+        if (rc != FUGLBM_OK) return rc;
+    }
     // odd parity first so that graph replays start from buffer 0
     if (left > 0 && s->parity == 1 && left >= 2 * GRAPH_STEPS) {
         hipError_t e = launch_one_step(s, s->parity, st);
@@ -732,7 +840,9 @@ std::map<std::pair<int, int>, BatchTable> &batch_tables() {
     return t;
 }
 
-fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, hipStream_t st) {
+// rows > 0: every member uses min(rows, ny) rows per item; 0: its own.
+fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, hipStream_t st,
+                          int rows = 0) {
     HIP_TRY(hipStreamSynchronize(st));  // the old table may still be read by queued launches
     if (bt.graph) {
         hipGraphExecDestroy(bt.graph);
@@ -750,11 +860,11 @@ fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group
         fs.parity = s->parity;
         hs.push_back(fs);
         const int strips = (s->nx + FUSED_OUT - 1) / FUSED_OUT;
-        const int chunks = (s->ny + s->rows - 1) / s->rows;
+        const int rw = rows > 0 ? std::min(rows, s->ny) : s->rows;
+        const int chunks = (s->ny + rw - 1) / rw;
         for (int c = 0; c < chunks; ++c)
             for (int t = 0; t < strips; ++t)
-                logical.push_back({(int32_t)k, t * FUSED_OUT, c * s->rows,
-                                   std::min(s->rows, s->ny - c * s->rows)});
+                logical.push_back({(int32_t)k, t * FUSED_OUT, c * rw, std::min(rw, s->ny - c * rw)});
     }
     const int n = (int)logical.size();
     const int per = (n + 7) / 8;
@@ -783,6 +893,38 @@ fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group
     bt.parity0.clear();
     for (auto *s : group) bt.parity0.push_back(s->parity);
     return FUGLBM_OK;
+}
+
+// Batched launches: the rows-per-item autotuner over one uniform rows value
+// for all members, cached per batch shape (component count, precision and
+// the multiset of grid sizes).  Leaves bt built with the chosen rows.
+fuglbm_status tune_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, int nc, bool f32,
+                         hipStream_t st) {
+    static std::map<std::vector<int>, int> cache;
+    for (auto *s : group)
+        if (!s->autotune) return build_batch(bt, group, st);   // rows fixed by the caller
+    std::vector<int> key = {nc, f32 ? 1 : 0};
+    std::vector<std::pair<int, int>> dims;
+    int ny_max = 1;
+    for (auto *s : group) {
+        dims.push_back({s->nx, s->ny});
+        ny_max = std::max(ny_max, s->ny);
+    }
+    std::sort(dims.begin(), dims.end());
+    for (auto &d : dims) {
+        key.push_back(d.first);
+        key.push_back(d.second);
+    }
+    auto hit = cache.find(key);
+    if (hit != cache.end()) return build_batch(bt, group, st, hit->second);
+    int best = 0;
+    fuglbm_status rc = time_candidates(
+        tune_candidates(ny_max, 0), st, [&](int r) { return build_batch(bt, group, st, r); },
+        [&]() { return launch_fused_d2q9(nc, f32, bt.ditems, bt.nitems, bt.dsims, 0, st); },
+        best);
+    if (rc != FUGLBM_OK) return rc;
+    cache[key] = best;
+    return build_batch(bt, group, st, best);
 }
 
 }  // namespace
@@ -841,14 +983,15 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             for (size_t k = 0; k < group.size(); ++k)
                 if ((group[k]->parity ^ bt.parity0[k]) != flip) same = false;
         }
-        if (!same) {
-            fuglbm_status rc = build_batch(bt, group, st);
-            if (rc != FUGLBM_OK) return rc;
-            flip = 0;
-        }
         const int nc = kv.first.first;
         const bool f32 = kv.first.second != 0;
         int64_t left = nsteps;
+        if (!same) {
+            fuglbm_status rc = left > 0 ? tune_batch(bt, group, nc, f32, st)
+                                        : build_batch(bt, group, st);
+            if (rc != FUGLBM_OK) return rc;
+            flip = 0;
+        }
         if (left >= 2 * GRAPH_STEPS && flip == 1) {
             hipError_t e = launch_fused_d2q9(nc, f32, bt.ditems, bt.nitems, bt.dsims, flip, st);
             if (e != hipSuccess) return hip_fail(e, "batched step launch");

@@ -37,8 +37,8 @@ def test_batched_equals_single_bitwise():
     from paper_2306_10652_amd import batch
     specs = small_specs()
     sw = batch.Sweep(specs, capi.FP32_STORAGE)
-    sw.step(37)
-    sw.step(163)      # graph-replayed runs + a remainder
+    sw.step(75)       # long enough to autotune rows for this batch shape
+    sw.step(125)      # graph-replayed runs + a remainder
     singles = batch.Sweep(specs, capi.FP32_STORAGE)
     singles.step_sequential(200)
     for a, b in zip(sw.sims, singles.sims):

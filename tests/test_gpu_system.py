@@ -138,3 +138,21 @@ def test_sticky_error_and_isolation_in_batch():
     rc = capi.fuglbm_step_many([a, b], 10)
     assert rc == 5                      # a skipped, b advanced
     assert np.array_equal(b.read_populations(), ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_state_independent_of_rows_per_item(precision):
+    """The autotuner times rows-per-item candidates on real steps: that is
+    only sound if every choice gives bitwise the same state."""
+    wl = W.random_droplet(4, (130, 75), seed=11)
+    fixed = []
+    for rows in (1, 5, 37):
+        sim = make(wl, precision)
+        sim.set_tuning(2, rows)
+        sim.step_n(150)
+        fixed.append(sim.read_populations())
+    tuned = make(wl, precision)       # autotuned during its first step_n
+    tuned.step_n(150)
+    ref = tuned.read_populations()
+    for g in fixed:
+        assert np.array_equal(g, ref)
