@@ -26,13 +26,16 @@
  *    never keeps a caller's host pointer.
  *  - A mixture must outlive every simulation made from it.  Handles are not
  *    thread-safe: use one handle from one thread at a time.
- *  - Populations are stored component-major, g[i][a][site] with
- *    site = x + nx*(y + ny*z), two buffers swapped every step.  FP32 storage
- *    keeps the rest populations g_{0,i} in FP64 (first, [ncomp][sites]) and
- *    the moving ones g_{a,i}, a >= 1, in FP32 (then [ncomp][Q-1][sites]);
- *    each step folds the FP32 rounding error of a site's moving populations
- *    into its rest population, so component masses are conserved to FP64
- *    rounding.  Arithmetic is FP64 in both precisions.
+ *  - Device populations are blocked by lattice row (row = y + ny*z, two
+ *    buffers swapped every step): row r holds the rest populations g_{0,i}
+ *    of all components as [ncomp][nx] doubles, then the moving ones
+ *    g_{a,i}, a >= 1, as [ncomp][Q-1][nx] values of the storage type
+ *    (double, or float with FP32 storage).  With FP32 storage each step
+ *    folds the rounding error of a site's moving populations into its rest
+ *    population, so component masses are conserved to FP64 rounding.
+ *    Arithmetic is FP64 in both precisions.  Host-side population arrays
+ *    (read/write_populations) are [ncomp][Q][sites] FP64, site = x +
+ *    nx*(y + ny*z).
  */
 #ifndef FUGLBM_H
 #define FUGLBM_H

@@ -99,8 +99,8 @@ static Carve carve(int N, int lat, bool fp32, int nx, int ny, int nz) {
     Carve c{};
     const int64_t ns = (int64_t)nx * ny * nz;
     const int Q = lattice_Q(lat), D = lattice_D(lat);
-    const size_t pop = align256((size_t)(fp32 ? pop_buffer_bytes<float>(N, Q, ns)
-                                              : pop_buffer_bytes<double>(N, Q, ns)));
+    const size_t pop = align256((size_t)(fp32 ? PopLayout<float>(N, Q, nx, (int64_t)ny * nz).bytes((int64_t)ny * nz)
+                                              : PopLayout<double>(N, Q, nx, (int64_t)ny * nz).bytes((int64_t)ny * nz)));
     size_t o = 0;
     c.buf0 = o; o += pop;
     c.buf1 = o; o += pop;
@@ -161,6 +161,18 @@ struct fuglbm_sim {
     GraphCache graph;
     uint64_t uid;          // never reused; batch tables key on it, not on the address
 };
+
+static int64_t pop_bytes(const fuglbm_sim *s) {
+    const int64_t rows = (int64_t)s->ny * s->nz;
+    return s->fp32 ? PopLayout<float>(s->N, s->Q, s->nx, rows).bytes(rows)
+                   : PopLayout<double>(s->N, s->Q, s->nx, rows).bytes(rows);
+}
+
+// The fused kernel indexes a buffer with 32-bit element offsets.
+static bool fused_fits(const fuglbm_sim *s) {
+    const int64_t elems = pop_bytes(s) / (s->fp32 ? 4 : 8);
+    return s->lattice == FUGLBM_D2Q9 && elems < ((int64_t)1 << 32);
+}
 
 static uint64_t next_sim_uid() {
     static uint64_t n = 0;
@@ -560,9 +572,10 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     fs.parity = 0;
     e = hipMemcpy(s->fsim, &fs, sizeof(FusedSim), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(e, "upload fused sim"));
-    s->kernel = lattice == FUGLBM_D2Q9 ? 2 : 1;
-    s->rows = lattice == FUGLBM_D2Q9 ? auto_rows(nx, ny, N, s->fp32) : 0;
-    if (lattice == FUGLBM_D2Q9) {
+    const bool fused = fused_fits(s);
+    s->kernel = fused ? 2 : 1;
+    s->rows = fused ? auto_rows(nx, ny, N, s->fp32) : 0;
+    if (fused) {
         rc = build_items(s);
         if (rc != FUGLBM_OK) return bail(rc);
     }
@@ -570,7 +583,7 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     s->snap_step = 0;
     s->have_snap = false;
     s->sticky = 0;
-    s->autotune = lattice == FUGLBM_D2Q9;
+    s->autotune = fused;
     s->tuned = false;
     s->uid = next_sim_uid();
     *out = s;
@@ -580,12 +593,12 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
     if (kernel < 0 || kernel > 2) return fail(FUGLBM_EINVAL, "kernel must be 0, 1 or 2");
-    if (kernel == 2 && s->lattice != FUGLBM_D2Q9)
-        return fail(FUGLBM_EINVAL, "the fused kernel is D2Q9 only");
+    if (kernel == 2 && !fused_fits(s))
+        return fail(FUGLBM_EINVAL, "the fused kernel is D2Q9 only, with < 2^32 elements per buffer");
     if (rows < 0) return fail(FUGLBM_EINVAL, "rows must be >= 0");
-    const int k = kernel == 0 ? (s->lattice == FUGLBM_D2Q9 ? 2 : 1) : kernel;
+    const int k = kernel == 0 ? (fused_fits(s) ? 2 : 1) : kernel;
     int r = s->rows;
-    if (s->lattice == FUGLBM_D2Q9) {
+    if (k == 2) {
         r = rows == 0 ? auto_rows(s->nx, s->ny, s->N, s->fp32) : std::min<int>(rows, s->ny);
         s->autotune = rows == 0;
         s->tuned = false;
@@ -607,9 +620,8 @@ fuglbm_status fuglbm_sim_info(const fuglbm_sim *s, int32_t *Q, int32_t *D, int64
     if (Q) *Q = s->Q;
     if (D) *D = s->D;
     if (sites) *sites = s->ns;
-    if (alg_bytes)
-        *alg_bytes = 2 * (s->fp32 ? pop_buffer_bytes<float>(s->N, s->Q, s->ns)
-                                  : pop_buffer_bytes<double>(s->N, s->Q, s->ns));
+    // algorithmic bytes: every population read and written once (no padding)
+    if (alg_bytes) *alg_bytes = 2 * (int64_t)s->N * s->ns * (8 + (s->Q - 1) * (s->fp32 ? 4 : 8));
     if (kernel) *kernel = s->kernel;
     return FUGLBM_OK;
 }
@@ -704,29 +716,54 @@ fuglbm_status fuglbm_diagnostics(fuglbm_sim *s, fuglbm_diag *diag) {
     return FUGLBM_OK;
 }
 
+extern "C++" {
+// Host copy of one buffer <-> [N][Q][sites] FP64 (the layout is PopLayout).
+template <typename ST>
+void unpack_pops(const fuglbm_sim *s, const char *buf, double *g) {
+    const PopLayout<ST> P(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz);
+    const int64_t rows = (int64_t)s->ny * s->nz;
+    for (int i = 0; i < s->N; ++i)
+        for (int a = 0; a < s->Q; ++a)
+            for (int64_t r = 0; r < rows; ++r) {
+                double *o = g + ((size_t)i * s->Q + a) * s->ns + (size_t)r * s->nx;
+                if (a == 0) {
+                    const double *src = (const double *)(buf + P.rest(r, i, 0));
+                    for (int x = 0; x < s->nx; ++x) o[x] = src[x];
+                } else {
+                    const ST *src = (const ST *)(buf + P.move(r, i, a, 0));
+                    for (int x = 0; x < s->nx; ++x) o[x] = (double)src[x];
+                }
+            }
+}
+
+template <typename ST>
+void pack_pops(const fuglbm_sim *s, const double *g, char *buf) {
+    const PopLayout<ST> P(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz);
+    const int64_t rows = (int64_t)s->ny * s->nz;
+    for (int i = 0; i < s->N; ++i)
+        for (int a = 0; a < s->Q; ++a)
+            for (int64_t r = 0; r < rows; ++r) {
+                const double *in = g + ((size_t)i * s->Q + a) * s->ns + (size_t)r * s->nx;
+                if (a == 0) {
+                    double *dst = (double *)(buf + P.rest(r, i, 0));
+                    for (int x = 0; x < s->nx; ++x) dst[x] = in[x];
+                } else {
+                    ST *dst = (ST *)(buf + P.move(r, i, a, 0));
+                    for (int x = 0; x < s->nx; ++x) dst[x] = (ST)in[x];
+                }
+            }
+}
+}  // extern "C++"
+
 fuglbm_status fuglbm_read_populations(fuglbm_sim *s, double *g_out) {
     if (!s || !g_out) return fail(FUGLBM_EINVAL, "null argument");
     HIP_TRY(hipStreamSynchronize(s->last_stream));
-    const size_t n = (size_t)s->N * s->Q * s->ns;
-    if (s->fp32) {
-        const int N = s->N, Q = s->Q;
-        const int64_t ns = s->ns;
-        std::vector<char> tmp((size_t)pop_buffer_bytes<float>(N, Q, ns));
-        HIP_TRY(hipMemcpy(tmp.data(), s->buf[s->parity], tmp.size(), hipMemcpyDeviceToHost));
-        const double *rest = (const double *)tmp.data();
-        const float *mov = (const float *)tmp.data();
-        for (int i = 0; i < N; ++i)
-            for (int a = 0; a < Q; ++a) {
-                double *o = g_out + ((size_t)i * Q + a) * ns;
-                if (a == 0)
-                    for (int64_t t = 0; t < ns; ++t) o[t] = rest[rest_offset<float>(Q, ns, i) + t];
-                else
-                    for (int64_t t = 0; t < ns; ++t)
-                        o[t] = (double)mov[move_offset<float>(N, Q, ns, i, a) + t];
-            }
-    } else {
-        HIP_TRY(hipMemcpy(g_out, s->buf[s->parity], n * 8, hipMemcpyDeviceToHost));
-    }
+    std::vector<char> tmp((size_t)pop_bytes(s));
+    HIP_TRY(hipMemcpy(tmp.data(), s->buf[s->parity], tmp.size(), hipMemcpyDeviceToHost));
+    if (s->fp32)
+        unpack_pops<float>(s, tmp.data(), g_out);
+    else
+        unpack_pops<double>(s, tmp.data(), g_out);
     return FUGLBM_OK;
 }
 
@@ -734,26 +771,12 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *s, const double *g_in, int64_
     if (!s || !g_in) return fail(FUGLBM_EINVAL, "null argument");
     if (step < 0) return fail(FUGLBM_EINVAL, "step must be >= 0");
     HIP_TRY(hipStreamSynchronize(s->last_stream));
-    const size_t n = (size_t)s->N * s->Q * s->ns;
-    if (s->fp32) {
-        const int N = s->N, Q = s->Q;
-        const int64_t ns = s->ns;
-        std::vector<char> tmp((size_t)pop_buffer_bytes<float>(N, Q, ns));
-        double *rest = (double *)tmp.data();
-        float *mov = (float *)tmp.data();
-        for (int i = 0; i < N; ++i)
-            for (int a = 0; a < Q; ++a) {
-                const double *g = g_in + ((size_t)i * Q + a) * ns;
-                if (a == 0)
-                    for (int64_t t = 0; t < ns; ++t) rest[rest_offset<float>(Q, ns, i) + t] = g[t];
-                else
-                    for (int64_t t = 0; t < ns; ++t)
-                        mov[move_offset<float>(N, Q, ns, i, a) + t] = (float)g[t];
-            }
-        HIP_TRY(hipMemcpy(s->buf[0], tmp.data(), tmp.size(), hipMemcpyHostToDevice));
-    } else {
-        HIP_TRY(hipMemcpy(s->buf[0], g_in, n * 8, hipMemcpyHostToDevice));
-    }
+    std::vector<char> tmp((size_t)pop_bytes(s));
+    if (s->fp32)
+        pack_pops<float>(s, g_in, tmp.data());
+    else
+        pack_pops<double>(s, g_in, tmp.data());
+    HIP_TRY(hipMemcpy(s->buf[0], tmp.data(), tmp.size(), hipMemcpyHostToDevice));
     s->parity = 0;
     s->step = step;
     s->have_snap = false;
@@ -766,15 +789,20 @@ fuglbm_status fuglbm_poke_population(fuglbm_sim *s, int32_t comp, int32_t a, int
     if (comp < 0 || comp >= s->N || a < 0 || a >= s->Q || site < 0 || site >= s->ns)
         return fail(FUGLBM_EINVAL, "index out of range");
     HIP_TRY(hipStreamSynchronize(s->last_stream));
-    if (s->fp32 && a > 0) {
+    const int64_t row = site / s->nx;
+    const int x = (int)(site - row * s->nx);
+    char *b = (char *)s->buf[s->parity];
+    if (a == 0) {
+        const int64_t off = s->fp32 ? PopLayout<float>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).rest(row, comp, x)
+                                    : PopLayout<double>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).rest(row, comp, x);
+        HIP_TRY(hipMemcpy(b + off, &value, 8, hipMemcpyHostToDevice));
+    } else if (s->fp32) {
         const float f = (float)value;
-        const int64_t k = move_offset<float>(s->N, s->Q, s->ns, comp, a) + site;
-        HIP_TRY(hipMemcpy((float *)s->buf[s->parity] + k, &f, 4, hipMemcpyHostToDevice));
+        const int64_t off = PopLayout<float>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).move(row, comp, a, x);
+        HIP_TRY(hipMemcpy(b + off, &f, 4, hipMemcpyHostToDevice));
     } else {
-        const int64_t k = (s->fp32 ? rest_offset<float>(s->Q, s->ns, comp)
-                                   : rest_offset<double>(s->Q, s->ns, comp) + (int64_t)a * s->ns) +
-                          site;
-        HIP_TRY(hipMemcpy((double *)s->buf[s->parity] + k, &value, 8, hipMemcpyHostToDevice));
+        const int64_t off = PopLayout<double>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).move(row, comp, a, x);
+        HIP_TRY(hipMemcpy(b + off, &value, 8, hipMemcpyHostToDevice));
     }
     return FUGLBM_OK;
 }

@@ -130,19 +130,30 @@ template <int NC, typename ST>
 struct Fused {
     FusedLds<NC> &L;
     cptr<SimConst> C;
+    // Population layout (PopLayout): bases of this component's rest array
+    // and of its direction-a arrays (at src[a - 1]) at row 0; row w is
+    // w * rsr doubles / w * rsm ST elements further on.
     gptr<double> srcR;
     gmptr<double> dstR;
-    gptr<ST> src[8];     // direction a at src[a - 1]
+    gptr<ST> src[8];
     gmptr<ST> dst[8];
+    uint32_t rsr, rsm;
     int comp, lane, nx, ny, xc, xm, xp, y0, rows;
     int wm3, wm2, wm1, w0;   // wrapped row indices of rows r-3 .. r (uniform)
     bool outl;
     double invM, bi, sqki, RT, invRT, omega, fcoef;
     uint32_t bad;
 
+    // An empty asm statement that reads every register of a row: the
+    // compiler must complete the row's loads before it.
+    __device__ __forceinline__ static void wait_row(const PopRow<ST> &g) {
+        asm volatile("" ::"v"(g.r), "v"(g.m[0]), "v"(g.m[1]), "v"(g.m[2]), "v"(g.m[3]), "v"(g.m[4]),
+                     "v"(g.m[5]), "v"(g.m[6]), "v"(g.m[7]));
+    }
+
     __device__ __forceinline__ void load_row(PopRow<ST> &g, int wrow) const {
-        const uint32_t off = (uint32_t)(wrow * nx + xc);
-        g.r = srcR[off];
+        g.r = srcR[(uint32_t)wrow * rsr + (uint32_t)xc];
+        const uint32_t off = (uint32_t)wrow * rsm + (uint32_t)xc;
 #pragma unroll
         for (int a = 0; a < 8; ++a) g.m[a] = src[a][off];
     }
@@ -270,6 +281,11 @@ struct Fused {
             L.tot[r & 3][2][lane] = jyt;
         }
         __syncthreads();
+        // Make the prefetched row resident here, before this row's stores:
+        // a wait for loads while stores are in flight waits for those
+        // stores too, and the ring rotation at the end of the row would
+        // otherwise wait for the stores just issued.
+        wait_row(gD);
         // ---- phase 3: velocity, collision and push of row y
         if (do_out) {
             double Fsx = 0.0, Fsy = 0.0;
@@ -290,9 +306,9 @@ struct Fused {
             const double Gu = Gx * ux + Gy * uy;
             const double K1 = fma(-0.5 * fcoef, Gu, base);
             const double K2 = fma(fcoef, Gu, base);
-            const uint32_t rowm = (uint32_t)(wm3 * nx);
-            const uint32_t row0 = (uint32_t)(wm2 * nx);
-            const uint32_t rowp = (uint32_t)(wm1 * nx);
+            const uint32_t rowm = (uint32_t)wm3 * rsm;
+            const uint32_t row0 = (uint32_t)wm2 * rsm;
+            const uint32_t rowp = (uint32_t)wm1 * rsm;
             if (outl) {
                 // the four opposite pairs, stored as they are formed; then the
                 // rest population, which in FP32 storage also takes the
@@ -319,7 +335,7 @@ struct Fused {
                 put(dst[7], rowm + xp, fma(omc, (double)gA.m[7], (1.0 / 36.0) * tm));
                 const double g0 =
                     fma(omc, gA.r, fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho));
-                dstR[row0 + xc] = sizeof(ST) == 4 ? g0 - err : g0;
+                dstR[(uint32_t)wm2 * rsr + (uint32_t)xc] = sizeof(ST) == 4 ? g0 - err : g0;
             }
         }
     }
@@ -341,17 +357,17 @@ __global__ __launch_bounds__(64 * NC) void k_fused_d2q9(const FusedItem *__restr
     f.lane = threadIdx.x & 63;
     f.nx = C->nx;
     f.ny = C->ny;
-    const int64_t ns = C->nsites;
     const char *bsrc = (const char *)(par ? sm->buf[1] : sm->buf[0]);
     char *bdst = (char *)(par ? sm->buf[0] : sm->buf[1]);
-    const int64_t ro = rest_offset<ST>(9, ns, f.comp);
-    f.srcR = (gptr<double>)((const double *)bsrc + ro);
-    f.dstR = (gmptr<double>)((double *)bdst + ro);
+    const PopLayout<ST> P(NC, 9, f.nx, f.ny);
+    f.rsr = (uint32_t)P.rest_row_stride();
+    f.rsm = (uint32_t)P.move_row_stride();
+    f.srcR = (gptr<double>)(const double *)(bsrc + P.rest(0, f.comp, 0));
+    f.dstR = (gmptr<double>)(double *)(bdst + P.rest(0, f.comp, 0));
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
-        const int64_t mo = move_offset<ST>(NC, 9, ns, f.comp, a);
-        f.src[a - 1] = (gptr<ST>)((const ST *)bsrc + mo);
-        f.dst[a - 1] = (gmptr<ST>)((ST *)bdst + mo);
+        f.src[a - 1] = (gptr<ST>)(const ST *)(bsrc + P.move(0, f.comp, a, 0));
+        f.dst[a - 1] = (gmptr<ST>)(ST *)(bdst + P.move(0, f.comp, a, 0));
     }
     int xc = (it.x0 - 2 + f.lane) % f.nx;
     if (xc < 0) xc += f.nx;

@@ -1,5 +1,5 @@
 // Three-pass step for any lattice (D2Q9, D3Q19), FP64 or FP32 storage
-// (population layouts: rest_offset / move_offset of the common header):
+// (population layout: PopLayout of the common header):
 //   pass 1  moments + local PR fugacity: rho_i, RT ln f_i, s = sum sqrt(kappa_j) rt_j, j
 //   pass 2  psi_i = RT ln f_i - sqrt(kappa_i) lap(s)             (Eq. (4)-(5))
 //   pass 3  F_i = -rt_i grad psi_i, G_i = grad rho_i, u, collide (Eq. (1)), push
@@ -55,11 +55,15 @@ __global__ __launch_bounds__(TPB) void k_init(const SimConst *__restrict__ c,
     const int64_t ns = c->nsites;
     const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (s >= ns) return;
-    const int N = c->N;
+    const int N = c->N, nx = c->nx;
+    const PopLayout<ST> P(N, L::Q, nx, (int64_t)c->ny * c->nz);
+    const int64_t row = s / nx;
+    const int x = (int)(s - row * nx);
+    char *b = (char *)g;
     for (int i = 0; i < N; ++i) {
-        ((double *)g)[rest_offset<ST>(L::Q, ns, i) + s] = rho[(int64_t)i * ns + s];
+        *(double *)(b + P.rest(row, i, x)) = rho[(int64_t)i * ns + s];
 #pragma unroll
-        for (int a = 1; a < L::Q; ++a) ((ST *)g)[move_offset<ST>(N, L::Q, ns, i, a) + s] = (ST)0;
+        for (int a = 1; a < L::Q; ++a) *(ST *)(b + P.move(row, i, a, x)) = (ST)0;
     }
 }
 
@@ -74,7 +78,10 @@ __global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict_
     const int64_t ns = c->nsites;
     const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (s >= ns) return;
-    const int N = c->N;
+    const int N = c->N, nx = c->nx;
+    const PopLayout<ST> P(N, L::Q, nx, (int64_t)c->ny * c->nz);
+    const int64_t row = s / nx;
+    const int xs = (int)(s - row * nx);
     double rt[FUG_MAXC];
     double jx = 0.0, jy = 0.0, jz = 0.0;
     double rtt = 0.0, eta = 0.0, sv = 0.0;
@@ -86,7 +93,7 @@ __global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict_
             double r = 0.0;
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) {
-                const double v = ld_pop<ST>(g, N, L::Q, ns, i, a, s);
+                const double v = ld_pop<ST>(g, P, row, i, a, xs);
                 r += v;
                 jx += L::ex(a) * v;
                 jy += L::ey(a) * v;
@@ -196,6 +203,9 @@ __global__ __launch_bounds__(TPB) void k_collide(const SimConst *__restrict__ c,
     site_velocity<L>(c, s, nb, rho_f, psi_f, j_f, ux, uy, uz, rhot);
     const double uu = ux * ux + uy * uy + uz * uz;
     const int N = c->N;
+    const PopLayout<ST> P(N, L::Q, nx, (int64_t)c->ny * c->nz);
+    const int64_t row = (int64_t)y + (int64_t)ny * z;
+    char *gdb = (char *)gd;
     const double omega = c->omega, fcoef = c->fcoef;
     for (int i = 0; i < N; ++i) {
         const double *ps = psi_f + (int64_t)i * ns;
@@ -213,17 +223,18 @@ __global__ __launch_bounds__(TPB) void k_collide(const SimConst *__restrict__ c,
         double err = 0.0;
 #pragma unroll
         for (int a = 1; a < L::Q; ++a) {
-            const double gv = ld_pop<ST>(gs, N, L::Q, ns, i, a, s);
+            const double gv = ld_pop<ST>(gs, P, row, i, a, x);
             const double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu,
                                             Gu, omega, fcoef);
             const ST v = (ST)o;
             if (sizeof(ST) == 4) err += (double)v - o;
-            ((ST *)gd)[move_offset<ST>(N, L::Q, ns, i, a) + nb[a]] = v;
+            const int64_t drow = nb[a] / nx;
+            *(ST *)(gdb + P.move(drow, i, a, (int)(nb[a] - drow * nx))) = v;
         }
-        const double g0 = ld_pop<ST>(gs, N, L::Q, ns, i, 0, s);
+        const double g0 = ld_pop<ST>(gs, P, row, i, 0, x);
         const double o0 = collide_one<L>(0, g0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
                                          omega, fcoef);
-        ((double *)gd)[rest_offset<ST>(L::Q, ns, i) + s] = sizeof(ST) == 4 ? o0 - err : o0;
+        *(double *)(gdb + P.rest(row, i, x)) = sizeof(ST) == 4 ? o0 - err : o0;
     }
 }
 
@@ -260,20 +271,23 @@ __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
                                               double *__restrict__ part, int use_snap) {
     __shared__ double red[TPB];
     const int64_t ns = c->nsites;
-    const int N = c->N;
+    const int N = c->N, nx = c->nx;
+    const PopLayout<ST> P(N, L::Q, nx, (int64_t)c->ny * c->nz);
     const int nq = 2 * N + 3;
     const int64_t stride = (int64_t)gridDim.x * TPB;
     double mass[FUG_MAXC], res[FUG_MAXC], mom[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < FUG_MAXC; ++i) mass[i] = res[i] = 0.0;
     for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < ns; s += stride) {
+        const int64_t row = s / nx;
+        const int x = (int)(s - row * nx);
 #pragma unroll
         for (int i = 0; i < FUG_MAXC; ++i) {
             if (i < N) {
                 double r = 0.0;
 #pragma unroll
                 for (int a = 0; a < L::Q; ++a) {
-                    const double v = ld_pop<ST>(g, N, L::Q, ns, i, a, s);
+                    const double v = ld_pop<ST>(g, P, row, i, a, x);
                     r += v;
                     mom[0] += L::ex(a) * v;
                     mom[1] += L::ey(a) * v;
