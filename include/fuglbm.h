@@ -173,7 +173,8 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int6
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *sim, int32_t kernel, int32_t rows);
 
 /* Query: Q, spatial dimension, sites, bytes moved per step by the
- * algorithm (2 Q N s per site), and the kernel in use. */
+ * algorithm (every population read and written once: 2 N (8 + (Q-1) s)
+ * per site, s = 8 for FP64 and 4 for FP32 storage), and the kernel in use. */
 fuglbm_status fuglbm_sim_info(const fuglbm_sim *sim, int32_t *Q, int32_t *D, int64_t *sites,
                               int64_t *alg_bytes_per_step, int32_t *kernel);
 

@@ -152,7 +152,7 @@ __device__ __forceinline__ double collide_one(int a, double g, double rho, doubl
 // (moving), so a workgroup's row of every component comes from one block;
 // the pitch is padded past large power-of-two strides.
 // FP32 storage: one array per (component, direction) over the whole grid,
-// [N][sites] double (rest) ++ [N][Q-1][sites] float (moving).
+// [N][sites + PAD] double (rest) ++ [N][Q-1][sites + PAD] float (moving).
 // (Both measured fastest for their precision with the fused D2Q9 kernel.)
 template <typename ST>
 struct PopLayout;
@@ -181,9 +181,11 @@ struct PopLayout<double> {
 
 template <>
 struct PopLayout<float> {
-    int64_t nx, ns, move_base, Qm;
+    static constexpr int64_t PAD = 64;   // elements between arrays (breaks power-of-two strides)
+    int64_t nx, ns, move_base, Qm;       // ns: array stride in elements
     __host__ __device__ PopLayout(int N, int Q, int nx_, int64_t rows)
-        : nx(nx_), ns(nx_ * rows), move_base((int64_t)N * nx_ * rows * 8), Qm(Q - 1) {}
+        : nx(nx_), ns(nx_ * rows + PAD), move_base((int64_t)N * (nx_ * rows + PAD) * 8),
+          Qm(Q - 1) {}
     __host__ __device__ int64_t rest(int64_t row, int i, int x) const {
         return ((int64_t)i * ns + row * nx + x) * 8;
     }

@@ -80,6 +80,8 @@ def test_fields_bytes():
     pop32 = 2 * (8 + 8 * 4) * 10 * 1024 * 1024
     # FP64 rows are padded to a pitch of 1024 + 16 (workspace is the same)
     pad64 = 2 * 9 * 10 * 8 * 16 * 1024
-    assert b64 >= pop64 and b64 - b32 == pop64 + pad64 - pop32
+    # FP32 arrays are 64 elements apart beyond the grid
+    pad32 = 2 * (8 + 8 * 4) * 10 * 64
+    assert b64 >= pop64 and b64 - b32 == pop64 + pad64 - pop32 - pad32
     assert L.fuglbm_fields_bytes(0, 0, 0, 8, 8, 1) == 0
     assert L.fuglbm_fields_bytes(3, 1, 0, 8, 8, 8) >= 2 * 19 * 3 * 8 * 512

@@ -81,8 +81,9 @@ def test_every_destination_written_nan_canary(precision):
     wl = W.random_droplet(4, (67, 33), seed=4)
     sim = make(wl, precision)
     Q, ns = 9, 67 * 33
-    # FP32 storage: FP64 rest populations, then FP32 moving ones
-    pop_bytes = 4 * ns * (8 + (Q - 1) * 4) if precision else 4 * Q * ns * 8
+    # FP32 storage: FP64 rest populations, then FP32 moving ones, arrays
+    # 64 elements apart beyond the grid; FP64 rows of 67 columns are unpadded
+    pop_bytes = 4 * (ns + 64) * (8 + (Q - 1) * 4) if precision else 4 * Q * ns * 8
     pop_bytes = (pop_bytes + 255) // 256 * 256
     base = (sim._buf.data_ptr() + 255) & ~255
     off = base - sim._buf.data_ptr() + pop_bytes
