@@ -44,15 +44,18 @@ def build_inputs(n):
     return C.N_ALKANES, 325.0, np.array(st["kij"]), rho
 
 
-def time_gpu(precision, steps, warmup, n, diag_every=100):
+def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0):
     import torch
     from paper_2306_10652_amd import capi
     comps, T, kij, rho = build_inputs(n)
     mix = capi.Mixture.from_components(comps, T, kij, kappa_ref=0.02, tau=1.0)
     stream = torch.cuda.Stream()
     sim = capi.Simulation(mix, capi.D2Q9, precision, (n, n), rho, stream=stream)
+    if rows:
+        sim.set_tuning(2, rows)         # fixed rows: no tuning launches (profiling runs)
     info = sim.info()
-    sim.step_n(warmup)
+    sim.step_n(warmup)                  # the first call autotunes rows (not timed)
+    tuning = sim.get_tuning()
     sim.diagnostics()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -79,16 +82,18 @@ def time_gpu(precision, steps, warmup, n, diag_every=100):
     alg = info["alg_bytes_per_step"]
     res = dict(csu=csu, wall=wall, ms_per_step=wall * 1e3 / steps, launch_ms=launch_s * 1e3,
                alg_bytes=alg, achieved_gbs=alg / launch_s / 1e9, kernel=info["kernel"],
+               rows=tuning["rows"],
                status=d["status"], residual=d["residual"], mass=d["mass"].tolist())
     sim.close()
     return res
 
 
-def sweep_leg(steps=512, acc_steps=20000, acc_count=8):
+def sweep_leg(steps=512, acc_steps=200000, acc_count=8):
     """Batched ternary sweep (256 C1/C3/nC10 instances, FP32 storage, one
     launch per step, graph-replayed) against the same instances stepped one
-    after another in plain FP64; accuracy of FP32 storage on a subset run to
-    acc_steps."""
+    after another in plain FP64.  Accuracy of FP32 storage at equilibrium:
+    thin slabs (64 x 4) of the first acc_count instances run acc_steps in
+    both precisions, bulk phases compared."""
     import torch
     from paper_2306_10652_amd import batch, capi
     from inputs import fields as Fi
@@ -96,7 +101,7 @@ def sweep_leg(steps=512, acc_steps=20000, acc_count=8):
     specs = batch.ternary_specs(S)
     st = torch.cuda.Stream()
     a = batch.Sweep(specs, capi.FP32_STORAGE, stream=st)
-    a.step(64)
+    a.step(64)                          # includes the batch's rows autotuning
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     a.step(steps)
@@ -112,8 +117,13 @@ def sweep_leg(steps=512, acc_steps=20000, acc_count=8):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     b.close()
-    # accuracy on a subset
-    sub = specs[:acc_count]
+    # accuracy at equilibrium on thin slabs of the first instances
+    sub = []
+    for sp, inst in zip(specs[:acc_count], S["instances"]):
+        sp = dict(sp)
+        sp["shape"] = (64, 4)
+        sp["rho"] = Fi.slab(64, 4, inst["rho_V"], inst["rho_L"], 0.5)
+        sub.append(sp)
     a = batch.Sweep(sub, capi.FP32_STORAGE, stream=st)
     b = batch.Sweep(sub, capi.FP64, stream=st)
     a.step(acc_steps)
@@ -131,8 +141,9 @@ def sweep_leg(steps=512, acc_steps=20000, acc_count=8):
                 fp64_sequential=dict(value=round(v_b, 1), unit="CSU/s",
                                      ms_per_step=round(tb / (steps // 4) * 1e3, 4)),
                 factor=round(v_a / v_b, 2),
-                fp32_vs_fp64=dict(instances=acc_count, steps=acc_steps, max_rel_phase_density=er,
-                                  max_abs_mole_fraction=ex))
+                fp32_vs_fp64_equilibrium=dict(instances=acc_count, grid=[64, 4], steps=acc_steps,
+                                              max_rel_phase_density=er,
+                                              max_abs_mole_fraction=ex))
 
 
 def time_vs_n_leg(steps=2000):
@@ -245,6 +256,9 @@ def main():
                     help="skip the sweep, time-vs-N and serving legs")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="fix the fused kernel's rows per work item instead of "
+                         "autotuning (profiling runs: no tuning launches)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times "
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -268,7 +282,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.precision != "both":
-        r = time_gpu(0 if args.precision == "fp64" else 1, args.steps, args.warmup, args.n)
+        r = time_gpu(0 if args.precision == "fp64" else 1, args.steps, args.warmup, args.n,
+                     rows=args.rows)
         print(json.dumps(dict(precision=args.precision, **{k: v for k, v in r.items()
                                                              if k != "mass"})), flush=True)
         return
@@ -278,7 +293,8 @@ def main():
     roof = dict(bound="hbm", achieved=round(r64["achieved_gbs"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4),
                 traffic=traffic, alg_bytes_per_launch=r64["alg_bytes"],
-                launch_ms=round(r64["launch_ms"], 5), kernel="k_fused_d2q9<10,double>")
+                launch_ms=round(r64["launch_ms"], 5), kernel="k_fused_d2q9<10,double>",
+                rows_per_item=r64["rows"])
     out = dict(metric="component-site updates/s & %HBM roofline; p50/p99 time-to-equilibrium",
                value=round(r64["csu"], 1),
                unit="CSU/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -292,7 +308,7 @@ def main():
                                  achieved_gbs=round(r32["achieved_gbs"], 1),
                                  frac=round(r32["achieved_gbs"] / HBM_PEAK_GBS, 4),
                                  alg_bytes_per_launch=r32["alg_bytes"],
-                                 launch_ms=round(r32["launch_ms"], 5)),
+                                 launch_ms=round(r32["launch_ms"], 5), rows_per_item=r32["rows"]),
                status=[r64["status"], r32["status"]])
     if not args.no_extra:
         out["batched_sweep"] = sweep_leg()

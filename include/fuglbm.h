@@ -172,6 +172,11 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int6
  * use, or rows < 0. */
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *sim, int32_t kernel, int32_t rows);
 
+/* Query the launch tuning in use: kernel (1 generic, 2 fused) and fused
+ * rows per work item (0 for the generic kernels; with autotuning, the
+ * value chosen once a step has run). */
+fuglbm_status fuglbm_get_tuning(const fuglbm_sim *sim, int32_t *kernel, int32_t *rows);
+
 /* Query: Q, spatial dimension, sites, bytes moved per step by the
  * algorithm (every population read and written once: 2 N (8 + (Q-1) s)
  * per site, s = 8 for FP64 and 4 for FP32 storage), and the kernel in use. */

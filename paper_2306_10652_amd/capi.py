@@ -24,7 +24,7 @@ EXPORTED = [
     "fuglbm_init_mixture", "fuglbm_lattice_constants", "fuglbm_destroy_mixture",
     "fuglbm_fields_bytes", "fuglbm_init_fields", "fuglbm_step_n", "fuglbm_step_many",
     "fuglbm_read_moments", "fuglbm_diagnostics", "fuglbm_read_populations",
-    "fuglbm_write_populations", "fuglbm_set_tuning", "fuglbm_sim_info",
+    "fuglbm_write_populations", "fuglbm_set_tuning", "fuglbm_get_tuning", "fuglbm_sim_info",
     "fuglbm_poke_population", "fuglbm_destroy_sim", "fuglbm_last_error",
 ]
 
@@ -90,6 +90,7 @@ def lib():
         "fuglbm_read_populations": ([vp, dp], i32),
         "fuglbm_write_populations": ([vp, dp, i64], i32),
         "fuglbm_set_tuning": ([vp, i32, i32], i32),
+        "fuglbm_get_tuning": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "fuglbm_sim_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
                              ctypes.POINTER(i64), ctypes.POINTER(i32)], i32),
         "fuglbm_poke_population": ([vp, i32, i32, i64, ctypes.c_double], i32),
@@ -248,6 +249,11 @@ class Simulation:
 
     def set_tuning(self, kernel=0, rows=0):
         check(lib().fuglbm_set_tuning(self.handle, int(kernel), int(rows)))
+
+    def get_tuning(self):
+        k, r = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().fuglbm_get_tuning(self.handle, ctypes.byref(k), ctypes.byref(r)))
+        return dict(kernel=k.value, rows=r.value)
 
     def info(self):
         Q, D, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

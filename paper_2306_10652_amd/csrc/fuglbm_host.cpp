@@ -590,6 +590,13 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     return FUGLBM_OK;
 }
 
+fuglbm_status fuglbm_get_tuning(const fuglbm_sim *s, int32_t *kernel, int32_t *rows) {
+    if (!s) return fail(FUGLBM_EINVAL, "null sim");
+    if (kernel) *kernel = s->kernel;
+    if (rows) *rows = s->kernel == 2 ? s->rows : 0;
+    return FUGLBM_OK;
+}
+
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
     if (kernel < 0 || kernel > 2) return fail(FUGLBM_EINVAL, "kernel must be 0, 1 or 2");
@@ -924,25 +931,32 @@ fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group
 }
 
 // Batched launches: the rows-per-item autotuner over one uniform rows value
-// for all members, cached per batch shape (component count, precision and
-// the multiset of grid sizes).  Leaves bt built with the chosen rows.
+// for all members, cached per batch class: component count, precision, and
+// the power-of-two classes of the total strip-rows (strips x ny summed over
+// members, which sets the item count against the resident slots) and of the
+// tallest member.  Batches of a serving loop change members often; a class
+// key lets them reuse one tuning.  Leaves bt built with the chosen rows.
+static int log2_class(int64_t v) {
+    int k = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++k;
+    }
+    return k;
+}
+
 fuglbm_status tune_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, int nc, bool f32,
                          hipStream_t st) {
-    static std::map<std::vector<int>, int> cache;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
     for (auto *s : group)
         if (!s->autotune) return build_batch(bt, group, st);   // rows fixed by the caller
-    std::vector<int> key = {nc, f32 ? 1 : 0};
-    std::vector<std::pair<int, int>> dims;
+    int64_t strip_rows = 0;
     int ny_max = 1;
     for (auto *s : group) {
-        dims.push_back({s->nx, s->ny});
+        strip_rows += (int64_t)((s->nx + FUSED_OUT - 1) / FUSED_OUT) * s->ny;
         ny_max = std::max(ny_max, s->ny);
     }
-    std::sort(dims.begin(), dims.end());
-    for (auto &d : dims) {
-        key.push_back(d.first);
-        key.push_back(d.second);
-    }
+    const auto key = std::make_tuple(nc, f32 ? 1 : 0, log2_class(strip_rows), log2_class(ny_max));
     auto hit = cache.find(key);
     if (hit != cache.end()) return build_batch(bt, group, st, hit->second);
     int best = 0;
