@@ -224,9 +224,9 @@ void drop_graph(fuglbm_sim *s) {
 hipError_t launch_one_step(fuglbm_sim *s, int flip_parity, hipStream_t st) {
     if (s->kernel == 2)
         return launch_fused_d2q9(s->N, s->fp32, s->items, s->nitems, s->fsim, flip_parity, st);
-    return launch_step_generic(s->lattice, s->fp32, s->dc, s->ns, s->buf[flip_parity],
+    return launch_step_generic(s->lattice, s->fp32, s->dc, s->N, s->nx, s->ny, s->nz, s->buf[flip_parity],
                                s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
-                               s->status, st);
+                               s->u_f, s->status, st);
 }
 
 constexpr int GRAPH_STEPS = 32;  // even: a replay returns to the same parity

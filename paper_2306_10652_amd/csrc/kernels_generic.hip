@@ -1,8 +1,9 @@
-// Three-pass step for any lattice (D2Q9, D3Q19), FP64 or FP32 storage
+// Multi-pass step for any lattice (D2Q9, D3Q19), FP64 or FP32 storage
 // (population layout: PopLayout of the common header):
 //   pass 1  moments + local PR fugacity: rho_i, RT ln f_i, s = sum sqrt(kappa_j) rt_j, j
 //   pass 2  psi_i = RT ln f_i - sqrt(kappa_i) lap(s)             (Eq. (4)-(5))
-//   pass 3  F_i = -rt_i grad psi_i, G_i = grad rho_i, u, collide (Eq. (1)), push
+//   pass 3  u = (j + F/2) / rho, F = -sum_i rt_i grad psi_i      (LDS tiles)
+//   pass 4  F_i, G_i = grad rho_i, collide (Eq. (1)), push        (LDS tiles)
 // One thread per site; fields between passes live in the simulation's
 // workspace.  Also: initial populations, the macroscopic read-out and the
 // per-block diagnostic partial sums.
@@ -185,35 +186,139 @@ __device__ __forceinline__ void site_velocity(const SimConst *c, int64_t s, cons
     uz = (L::D == 3) ? (j_f[2 * ns + s] + 0.5 * Fz) / rhot : 0.0;
 }
 
-template <class L, typename ST>
-__global__ __launch_bounds__(TPB) void k_collide(const SimConst *__restrict__ c,
-                                                 const void *__restrict__ gs, void *__restrict__ gd,
-                                                 const double *__restrict__ rho_f,
-                                                 const double *__restrict__ psi_f,
-                                                 const double *__restrict__ j_f) {
-    const int64_t ns = c->nsites;
-    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (s >= ns) return;
-    const int nx = c->nx, ny = c->ny, nz = c->nz;
-    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((int64_t)nx * ny));
-    int64_t nb[L::Q];
+// ---- LDS-tiled force, velocity and collision --------------------------------
+// A workgroup owns a tile of TX x TY x TZ sites (one thread per site) and,
+// one component at a time, stages psi_i and rho_i over the tile plus a
+// one-site halo in LDS, so every neighbour value is read from HBM/L2 once
+// per tile instead of once per neighbour.
+template <class L> struct Tile;
+template <> struct Tile<D2Q9> { static constexpr int TX = 64, TY = 4, TZ = 1, HZ = 0; };
+template <> struct Tile<D3Q19> { static constexpr int TX = 16, TY = 4, TZ = 4, HZ = 1; };
+
+template <class L>
+struct TileGeom {
+    static constexpr int TX = Tile<L>::TX, TY = Tile<L>::TY, TZ = Tile<L>::TZ, HZ = Tile<L>::HZ;
+    static constexpr int HX = TX + 2, HY = TY + 2, HZN = TZ + 2 * HZ;
+    static constexpr int NH = HX * HY * HZN;   // halo tile points
+    static_assert(TX * TY * TZ == TPB, "one thread per tile site");
+    int x0, y0, z0, lx, ly, lz, x, y, z;
+    bool active;
+    int lc;   // LDS index of this thread's site
+    __device__ TileGeom(const SimConst *c) {
+        const int ntx = (c->nx + TX - 1) / TX, nty = (c->ny + TY - 1) / TY;
+        const int b = blockIdx.x;
+        x0 = (b % ntx) * TX;
+        y0 = ((b / ntx) % nty) * TY;
+        z0 = (b / (ntx * nty)) * TZ;
+        const int t = threadIdx.x;
+        lx = t % TX;
+        ly = (t / TX) % TY;
+        lz = t / (TX * TY);
+        x = x0 + lx;
+        y = y0 + ly;
+        z = z0 + lz;
+        active = x < c->nx && y < c->ny && z < c->nz;
+        lc = ((lz + HZ) * HY + (ly + 1)) * HX + (lx + 1);
+    }
+    __device__ static int lds_off(int a) { return (L::ez(a) * HY + L::ey(a)) * HX + L::ex(a); }
+    // stage field f (one component plane of ns values) into lds[NH]
+    __device__ void stage(const SimConst *c, const double *f, double *lds) const {
+        const int nx = c->nx, ny = c->ny, nz = c->nz;
+        for (int k = threadIdx.x; k < NH; k += TPB) {
+            const int hx = k % HX, hy = (k / HX) % HY, hz = k / (HX * HY);
+            int gx = (x0 - 1 + hx) % nx, gy = (y0 - 1 + hy) % ny, gz = (z0 - HZ + hz) % nz;
+            if (gx < 0) gx += nx;
+            if (gy < 0) gy += ny;
+            if (gz < 0) gz += nz;
+            lds[k] = f[(int64_t)gx + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz)];
+        }
+    }
+    __device__ void grad(const double *lds, double &gx, double &gy, double &gz) const {
+        int nb[L::Q];
 #pragma unroll
-    for (int a = 0; a < L::Q; ++a) nb[a] = nb_site<L>(x, y, z, a, nx, ny, nz);
-    double ux, uy, uz, rhot;
-    site_velocity<L>(c, s, nb, rho_f, psi_f, j_f, ux, uy, uz, rhot);
+        for (int a = 0; a < L::Q; ++a) nb[a] = lc + lds_off(a);
+        int64_t nb64[L::Q];
+#pragma unroll
+        for (int a = 0; a < L::Q; ++a) nb64[a] = nb[a];
+        lattice_grad<L>(nb64, [&](int64_t t) { return lds[t]; }, gx, gy, gz);
+    }
+};
+
+inline unsigned tile_blocks(int lattice, int nx, int ny, int nz) {
+    const int TX = lattice == 0 ? Tile<D2Q9>::TX : Tile<D3Q19>::TX;
+    const int TY = lattice == 0 ? Tile<D2Q9>::TY : Tile<D3Q19>::TY;
+    const int TZ = lattice == 0 ? Tile<D2Q9>::TZ : Tile<D3Q19>::TZ;
+    return (unsigned)(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ));
+}
+
+// u = (j + F/2) / rho, F = sum_i F_i, F_i = -rt_i grad psi_i  -> u_f
+template <class L>
+__global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__ c,
+                                                    const double *__restrict__ rho_f,
+                                                    const double *__restrict__ psi_f,
+                                                    const double *__restrict__ j_f,
+                                                    double *__restrict__ u_f) {
+    __shared__ double lp[TileGeom<L>::NH];
+    const TileGeom<L> T(c);
+    const int64_t ns = c->nsites;
+    const int64_t s = T.active ? (int64_t)T.x + (int64_t)c->nx * ((int64_t)T.y + (int64_t)c->ny * T.z) : 0;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, rhot = 0.0;
+    for (int i = 0; i < c->N; ++i) {
+        __syncthreads();
+        T.stage(c, psi_f + (int64_t)i * ns, lp);
+        __syncthreads();
+        if (T.active) {
+            double gx, gy, gz;
+            T.grad(lp, gx, gy, gz);
+            const double r = rho_f[(int64_t)i * ns + s];
+            const double rt = r * c->invM[i];
+            Fx -= rt * gx;
+            Fy -= rt * gy;
+            Fz -= rt * gz;
+            rhot += r;
+        }
+    }
+    if (!T.active) return;
+    u_f[s] = (j_f[s] + 0.5 * Fx) / rhot;
+    u_f[ns + s] = (j_f[ns + s] + 0.5 * Fy) / rhot;
+    if (L::D == 3) u_f[2 * ns + s] = (j_f[2 * ns + s] + 0.5 * Fz) / rhot;
+}
+
+// collision (Eq. (1a)-(1c)) and push of component blockIdx.y; u from u_f
+template <class L, typename ST>
+__global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ c,
+                                                   const void *__restrict__ gs, void *__restrict__ gd,
+                                                   const double *__restrict__ rho_f,
+                                                   const double *__restrict__ psi_f,
+                                                   const double *__restrict__ u_f) {
+    __shared__ double lp[TileGeom<L>::NH];
+    __shared__ double lr[TileGeom<L>::NH];
+    const TileGeom<L> T(c);
+    const int64_t ns = c->nsites;
+    const int nx = c->nx, ny = c->ny, nz = c->nz, N = c->N;
+    const int64_t s = T.active ? (int64_t)T.x + (int64_t)nx * ((int64_t)T.y + (int64_t)ny * T.z) : 0;
+    const PopLayout<ST> P(N, L::Q, nx, (int64_t)ny * nz);
+    const int64_t row = (int64_t)T.y + (int64_t)ny * T.z;
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    if (T.active) {
+        ux = u_f[s];
+        uy = u_f[ns + s];
+        uz = (L::D == 3) ? u_f[2 * ns + s] : 0.0;
+    }
     const double uu = ux * ux + uy * uy + uz * uz;
-    const int N = c->N;
-    const PopLayout<ST> P(N, L::Q, nx, (int64_t)c->ny * c->nz);
-    const int64_t row = (int64_t)y + (int64_t)ny * z;
-    char *gdb = (char *)gd;
     const double omega = c->omega, fcoef = c->fcoef;
-    for (int i = 0; i < N; ++i) {
-        const double *ps = psi_f + (int64_t)i * ns;
-        const double *rs = rho_f + (int64_t)i * ns;
+    const char *gsb = (const char *)gs;
+    char *gdb = (char *)gd;
+    const int i = blockIdx.y;
+    {
+        T.stage(c, psi_f + (int64_t)i * ns, lp);
+        T.stage(c, rho_f + (int64_t)i * ns, lr);
+        __syncthreads();
+        if (!T.active) return;
         double gx, gy, gz, Gx, Gy, Gz;
-        lattice_grad<L>(nb, [&](int64_t t) { return ps[t]; }, gx, gy, gz);
-        lattice_grad<L>(nb, [&](int64_t t) { return rs[t]; }, Gx, Gy, Gz);
-        const double r = rs[s];
+        T.grad(lp, gx, gy, gz);
+        T.grad(lr, Gx, Gy, Gz);
+        const double r = lr[T.lc];
         const double rt = r * c->invM[i];
         const double Fx = -rt * gx, Fy = -rt * gy, Fz = -rt * gz;
         const double Fu = Fx * ux + Fy * uy + Fz * uz;
@@ -221,20 +326,25 @@ __global__ __launch_bounds__(TPB) void k_collide(const SimConst *__restrict__ c,
         // moving populations first; in FP32 storage their rounding error
         // goes into the rest population, which stays at this site
         double err = 0.0;
-#pragma unroll
+        // directions in a rolled loop: unrolled, the compiler hoists every
+        // load and the kernel needs 256 registers (one wavefront per SIMD)
+#pragma unroll 2
         for (int a = 1; a < L::Q; ++a) {
-            const double gv = ld_pop<ST>(gs, P, row, i, a, x);
+            const double gv = (double)*(const ST *)(gsb + P.move(row, i, a, T.x));
             const double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu,
                                             Gu, omega, fcoef);
             const ST v = (ST)o;
             if (sizeof(ST) == 4) err += (double)v - o;
-            const int64_t drow = nb[a] / nx;
-            *(ST *)(gdb + P.move(drow, i, a, (int)(nb[a] - drow * nx))) = v;
+            int xx = T.x + L::ex(a), yy = T.y + L::ey(a), zz = T.z + L::ez(a);
+            xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+            yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+            zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+            *(ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)) = v;
         }
-        const double g0 = ld_pop<ST>(gs, P, row, i, 0, x);
+        const double g0 = *(const double *)(gsb + P.rest(row, i, T.x));
         const double o0 = collide_one<L>(0, g0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
                                          omega, fcoef);
-        *(double *)(gdb + P.rest(row, i, x)) = sizeof(ST) == 4 ? o0 - err : o0;
+        *(double *)(gdb + P.rest(row, i, T.x)) = sizeof(ST) == 4 ? o0 - err : o0;
     }
 }
 
@@ -322,15 +432,17 @@ __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
 inline unsigned nblocks(int64_t ns) { return (unsigned)((ns + TPB - 1) / TPB); }
 
 template <class L, typename ST>
-hipError_t step_generic_t(const SimConst *c, int64_t ns, const void *gs, void *gd, double *rho_f,
-                          double *psi_f, double *s_f, double *j_f, uint32_t *status,
-                          hipStream_t st) {
+hipError_t step_generic_t(const SimConst *c, int ncomp, int64_t ns, int nx, int ny, int nz,
+                          const void *gs, void *gd, double *rho_f, double *psi_f, double *s_f,
+                          double *j_f, double *u_f, uint32_t *status, hipStream_t st) {
     const unsigned nb = nblocks(ns);
+    const unsigned tb = tile_blocks(L::D == 2 ? 0 : 1, nx, ny, nz);
     hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, gs, rho_f, psi_f,
                        s_f, j_f, status);
     hipLaunchKernelGGL((k_interface<L>), dim3(nb), dim3(TPB), 0, st, c, s_f, psi_f);
-    hipLaunchKernelGGL((k_collide<L, ST>), dim3(nb), dim3(TPB), 0, st, c, gs, gd, rho_f, psi_f,
-                       j_f);
+    hipLaunchKernelGGL((k_velocity_t<L>), dim3(tb), dim3(TPB), 0, st, c, rho_f, psi_f, j_f, u_f);
+    hipLaunchKernelGGL((k_collide_t<L, ST>), dim3(tb, ncomp), dim3(TPB), 0, st, c, gs, gd, rho_f,
+                       psi_f, u_f);
     return hipGetLastError();
 }
 
@@ -363,14 +475,16 @@ hipError_t launch_init(int lattice, bool fp32, const SimConst *c, int64_t ns, co
     return hipGetLastError();
 }
 
-hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int64_t ns,
-                               const void *gs, void *gd, double *rho_f, double *psi_f,
-                               double *s_f, double *j_f, uint32_t *status, hipStream_t st) {
+hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int ncomp, int nx, int ny,
+                               int nz, const void *gs, void *gd, double *rho_f, double *psi_f,
+                               double *s_f, double *j_f, double *u_f, uint32_t *status,
+                               hipStream_t st) {
+    const int64_t ns = (int64_t)nx * ny * nz;
     if (lattice == 0)
-        return fp32 ? step_generic_t<D2Q9, float>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st)
-                    : step_generic_t<D2Q9, double>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st);
-    return fp32 ? step_generic_t<D3Q19, float>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st)
-                : step_generic_t<D3Q19, double>(c, ns, gs, gd, rho_f, psi_f, s_f, j_f, status, st);
+        return fp32 ? step_generic_t<D2Q9, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st)
+                    : step_generic_t<D2Q9, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st);
+    return fp32 ? step_generic_t<D3Q19, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st)
+                : step_generic_t<D3Q19, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st);
 }
 
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
