@@ -844,6 +844,8 @@ struct BatchTable {
     size_t cap_sims = 0, cap_items = 0;
     int nitems = 0;
     hipGraphExec_t graph = nullptr;   // GRAPH_STEPS launches starting at flip 0
+    hipStream_t last_stream = nullptr;
+    bool used = false;                // last_stream is meaningful
 };
 
 fuglbm_status batch_graph(BatchTable &bt, int ncomp, bool fp32) {
@@ -1016,6 +1018,11 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
     for (auto &kv : groups) {
         auto &group = kv.second;
         BatchTable &bt = batch_tables()[kv.first];
+        // the table (and its graph) is shared state: launches queued on
+        // another stream must finish before this call rebuilds or reuses it
+        if (bt.used && bt.last_stream != st) HIP_TRY(hipStreamSynchronize(bt.last_stream));
+        bt.last_stream = st;
+        bt.used = true;
         bool same = bt.sims.size() == group.size();
         for (size_t k = 0; same && k < group.size(); ++k)
             same = bt.sims[k] == group[k] && bt.uids[k] == group[k]->uid;

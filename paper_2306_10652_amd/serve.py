@@ -4,11 +4,14 @@ Requests (a mixture, a lattice and grid, an initial field) arrive over time.
 A request is admitted as soon as its device memory fits the HBM budget and
 a slot is free; from then on it shares the GPU with every other admitted
 request: each tick advances all active D2Q9 simulations with one batched
-launch per step (``fuglbm_step_many``, grouped by component count) and the
-D3Q19 ones with their own launches, all on one stream, then reads every
-simulation's residual (``fuglbm_diagnostics``).  A simulation retires when
-its residual R_K <= tol (K = steps per tick) or at its step cap; its fields
-are read back and its memory returned, and waiting requests are admitted.
+launch per step per component count (``fuglbm_step_many``) and the D3Q19
+ones with their own launches.  These units of work go round-robin onto a
+few HIP streams (default priority), so small launches of different groups
+run side by side on the CUs; then every simulation's residual is read
+(``fuglbm_diagnostics``, on the stream that stepped it).  A simulation
+retires when its residual R_K <= tol (K = steps per tick) or at its step
+cap; its fields are read back and its memory returned, and waiting
+requests are admitted.
 
 Latency = finish - arrival, service = finish - admit, both wall clock.
 """
@@ -57,7 +60,7 @@ class Request:
 
 class Server:
     def __init__(self, hbm_budget_bytes, chunk=200, max_active=64, kappa_ref=0.02,
-                 keep_fields=False, stream=None):
+                 keep_fields=False, stream=None, streams=4):
         import torch
         self.budget = int(hbm_budget_bytes)
         self.chunk = int(chunk)
@@ -65,6 +68,7 @@ class Server:
         self.kappa_ref = kappa_ref
         self.keep_fields = keep_fields
         self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.streams = [self.stream] + [torch.cuda.Stream() for _ in range(max(0, streams - 1))]
         self.used = 0
         self.done = []
 
@@ -124,18 +128,28 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, min(0.05, pending[0][0] - (clock() - t0))))
                 continue
-            # one tick: every active simulation advances `chunk` steps
-            d2 = [s for s in active if s["req"].lattice == capi.D2Q9]
-            d3 = [s for s in active if s["req"].lattice != capi.D2Q9]
-            if d2:
-                rc = capi.fuglbm_step_many([s["sim"] for s in d2], self.chunk, self.stream)
-                if rc not in (0, 5):
-                    capi.check(rc)
-            for s in d3:
-                try:
-                    s["sim"].step_n(self.chunk)
-                except capi.FuglbmError:
-                    pass
+            # one tick: every active simulation advances `chunk` steps; units
+            # of work (a batched D2Q9 group, a D3Q19 simulation) round-robin
+            # over the streams
+            groups = {}
+            units = []
+            for s in active:
+                if s["req"].lattice == capi.D2Q9:
+                    groups.setdefault((s["req"].N, s["req"].precision), []).append(s)
+                else:
+                    units.append([s])
+            units = list(groups.values()) + units
+            for k, unit in enumerate(units):
+                st = self.streams[k % len(self.streams)]
+                if unit[0]["req"].lattice == capi.D2Q9:
+                    rc = capi.fuglbm_step_many([s["sim"] for s in unit], self.chunk, st)
+                    if rc not in (0, 5):
+                        capi.check(rc)
+                else:
+                    try:
+                        unit[0]["sim"].step_n(self.chunk, st)
+                    except capi.FuglbmError:
+                        pass
             still = []
             for s in active:
                 req = s["req"]
