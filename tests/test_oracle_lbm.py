@@ -185,3 +185,38 @@ def test_flat_interface_relaxes_to_maxwell(oracle_lib):
     assert abs(rt[0] / rV - 1) < 2e-5
     assert abs(rt[64] / rL - 1) < 2e-5
     assert np.abs(fl["u"]).max() < 1e-9
+
+
+def test_d3q19_reduces_to_d2q9_on_a_one_dimensional_field(oracle_lib):
+    """A field that varies along x only: D2Q9 and D3Q19 both reduce to the
+    same three-velocity lattice along x (weights 2/3, 1/6, 1/6; the same
+    isotropic second-order forcing), so the two oracles give the same
+    densities.  Pins the D3Q19 velocity set, weights and the D-dependent
+    forcing term against the D2Q9 ones."""
+    comps, T, _ = C.table_ii_components(3)
+    mix = lbm.oracle_mixture(comps, T)
+    st = Fi.load_phase_states()["vle3"]
+    f2 = Fi.slab(64, 1, st["rho_V"], st["rho_L"], 0.5)
+    a = lbm.OracleLBM(mix, 0, (64, 1), f2)
+    b = lbm.OracleLBM(mix, 1, (64, 1, 1), f2)      # [N][nz=1][ny=1][nx]
+    a.run(2000)
+    b.run(2000)
+    ra = a.rho().reshape(len(comps), -1)
+    rb = b.rho().reshape(len(comps), -1)
+    assert np.max(np.abs(ra - rb)) / np.max(np.abs(ra)) < 1e-12
+
+
+def test_d3q19_flat_interface_relaxes_to_maxwell(oracle_lib):
+    """Table II case 1 on a 128 x 1 x 1 D3Q19 slab: the bulk densities reach
+    the Maxwell coexistence densities (even windows) with u at round-off."""
+    c1 = C.TABLE_I["C1"]
+    mix = lbm.oracle_mixture([c1], 177.24)
+    ps, rV, rL = th.maxwell(mix.pr)
+    f = Fi.slab(128, 1, [0.98 * rV], [1.02 * rL], 0.5).reshape(1, 1, 1, 128)
+    sim = lbm.OracleLBM(mix, 1, (128, 1, 1), f)
+    sim.run(20000)
+    fl = sim.fields()
+    rt = fl["rho"].reshape(-1) / mix.M[0]
+    assert abs(rt[0:4].mean() / rV - 1) < 2e-5
+    assert abs(rt[62:66].mean() / rL - 1) < 2e-5
+    assert np.abs(fl["u"]).max() < 1e-9
