@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the sweep, time-vs-N and serving legs")
+    ap.add_argument("--legs", default="sweep,time_vs_n,serving",
+                    help="comma-separated extra legs to run (sweep, time_vs_n, serving)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
     ap.add_argument("--rows", type=int, default=0,
@@ -310,11 +312,14 @@ def main():
                                  alg_bytes_per_launch=r32["alg_bytes"],
                                  launch_ms=round(r32["launch_ms"], 5), rows_per_item=r32["rows"]),
                status=[r64["status"], r32["status"]])
-    if not args.no_extra:
+    legs = set() if args.no_extra else set(args.legs.split(","))
+    if "sweep" in legs:
         out["batched_sweep"] = sweep_leg()
+    if "time_vs_n" in legs:
         out["time_vs_N"] = time_vs_n_leg()
-        out["serving"] = serving_leg(
-            capacity_csu_s=out["batched_sweep"]["fp32_batched"]["value"])
+    if "serving" in legs:
+        cap = out["batched_sweep"]["fp32_batched"]["value"] if "batched_sweep" in out else None
+        out["serving"] = serving_leg(capacity_csu_s=cap)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -5,9 +5,9 @@ A request is admitted as soon as its device memory fits the HBM budget and
 a slot is free; from then on it shares the GPU with every other admitted
 request: each tick advances all active D2Q9 simulations with one batched
 launch per step per component count (``fuglbm_step_many``) and the D3Q19
-ones with their own launches.  These units of work go round-robin onto a
-few HIP streams (default priority), so small launches of different groups
-run side by side on the CUs; then every simulation's residual is read
+ones with their own launches.  These units of work go longest-first onto
+the least-loaded of a few HIP streams (default priority), so launches of
+different groups run side by side on the CUs; then every simulation's residual is read
 (``fuglbm_diagnostics``, on the stream that stepped it).  A simulation
 retires when its residual R_K <= tol (K = steps per tick) or at its step
 cap; its fields are read back and its memory returned, and waiting
@@ -60,7 +60,7 @@ class Request:
 
 class Server:
     def __init__(self, hbm_budget_bytes, chunk=200, max_active=64, kappa_ref=0.02,
-                 keep_fields=False, stream=None, streams=4):
+                 keep_fields=False, stream=None, streams=6):
         import torch
         self.budget = int(hbm_budget_bytes)
         self.chunk = int(chunk)
@@ -139,8 +139,14 @@ class Server:
                 else:
                     units.append([s])
             units = list(groups.values()) + units
-            for k, unit in enumerate(units):
-                st = self.streams[k % len(self.streams)]
+            # longest-first onto the least-loaded stream (work ~ CSU per step)
+            cost = lambda u: sum(int(np.prod(s["req"].shape)) * s["req"].N *
+                                 (19 if s["req"].lattice != capi.D2Q9 else 9) for s in u)
+            load = [0] * len(self.streams)
+            for unit in sorted(units, key=cost, reverse=True):
+                k = min(range(len(load)), key=load.__getitem__)
+                load[k] += cost(unit)
+                st = self.streams[k]
                 if unit[0]["req"].lattice == capi.D2Q9:
                     rc = capi.fuglbm_step_many([s["sim"] for s in unit], self.chunk, st)
                     if rc not in (0, 5):
