@@ -181,3 +181,40 @@ def test_young_laplace_linear_in_inverse_radius():
     report("young_laplace_fit", sigma=sigma, intercept=c0, r2=r2)
     assert sigma > 0 and r2 > 0.999
     assert abs(c0) < 0.05 * dp.max()
+
+
+def test_ternary_sweep_slabs_reach_phase_equilibrium():
+    """Batched ternary slabs (C1/C3/nC10, the sweep's own states on thin
+    64 x 4 grids, FP64, one launch per step for all of them) reach the
+    stationary state of the scheme: the fugacity of every component is the
+    same in the two bulk phases (Eq. (12) via the oracle's thermodynamics).
+    The bulk pressures then differ by the discrete scheme's thermodynamic
+    inconsistency across the interface (the continuum Gibbs-Duhem integral
+    through the interface vanishes, its lattice sum does not exactly); it is
+    bounded loosely, on the liquid's pressure scale rho RT."""
+    capi = _capi()
+    from paper_2306_10652_amd import batch
+    from oracle.lbm import oracle_mixture
+    S = W.states()["ternary_sweep"]
+    specs = []
+    for sp, inst in zip(batch.ternary_specs(S, count=4), S["instances"]):
+        sp = dict(sp)
+        sp["shape"] = (64, 4)
+        sp["rho"] = Fi.slab(64, 4, inst["rho_V"], inst["rho_L"], 0.5)
+        specs.append(sp)
+    sw = batch.Sweep(specs, capi.FP64)
+    sw.step(200000)
+    worst_p, worst_f = 0.0, 0.0
+    for sp, sim, inst in zip(specs, sw.sims, S["instances"]):
+        om = oracle_mixture(C.TERNARY_C1_C3_C10, inst["T"])
+        rt = sim.read_moments(velocity=False)["rho"][:, 0, :, :] / om.M[:, None, None]
+        vap = np.concatenate([rt[:, :, 0:4], rt[:, :, 60:64]], axis=2).mean(axis=(1, 2))
+        liq = rt[:, :, 28:36].mean(axis=(1, 2))
+        pV, pL = om.pr.pressure_rho(vap), om.pr.pressure_rho(liq)
+        dlnf = np.abs(om.pr.ln_fugacity_rho(liq) - om.pr.ln_fugacity_rho(vap))
+        worst_p = max(worst_p, abs(pL - pV) / (liq.sum() * om.RT))
+        worst_f = max(worst_f, float(dlnf.max()))
+    report("ternary_equilibrium", instances=len(specs), dp_over_rhoRT=worst_p, dlnf=worst_f)
+    sw.close()
+    assert worst_f < 1e-4
+    assert worst_p < 1e-2
