@@ -67,3 +67,23 @@ TABLE_II = {
 def table_ii_components(case):
     names, T, p = TABLE_II[case]
     return [TABLE_I[n] for n in names], T, p
+
+
+# Paper, Section III.E, Table VII: the ten-component mixture (Table I
+# components) with its overall composition and the CO2 binary interaction
+# parameters (all other pairs zero).  Ordered with C1 first, the component
+# that anchors the lattice units (Section III.E fixes a, b and M of C1).
+TEN_CO2_NAMES = ["C1", "C2", "C3", "iC4", "C4", "iC5", "C5", "C6", "C7+", "CO2"]
+TEN_CO2 = [TABLE_I[n] for n in TEN_CO2_NAMES]
+TEN_CO2_Z = [0.6192, 0.1408, 0.0835, 0.0097, 0.0341, 0.0084, 0.0148, 0.0179, 0.0685, 0.0031]
+TEN_CO2_KIJ_CO2 = [0.105, 0.130, 0.125, 0.120, 0.115, 0.115, 0.115, 0.115, 0.115, 0.0]
+
+
+def ten_co2_kij():
+    """Symmetric k_ij matrix of the Table VII mixture (TEN_CO2 order)."""
+    n = len(TEN_CO2)
+    k = [[0.0] * n for _ in range(n)]
+    c = TEN_CO2_NAMES.index("CO2")
+    for i in range(n):
+        k[i][c] = k[c][i] = TEN_CO2_KIJ_CO2[i]
+    return k

@@ -1,7 +1,9 @@
 """Write ``inputs/phase_states.json``: the phase densities every synthetic
 workload starts from, computed by the oracle's own flash / Maxwell code.
 
-Run: ``python -m oracle.write_phase_states`` (from the repository root).
+Run: ``python -m oracle.write_phase_states`` (from the repository root);
+``python -m oracle.write_phase_states ten_co2`` refreshes only the
+ten-component CO2 states.
 Only ``oracle/`` and the seeded draws in ``inputs/`` are used; nothing comes
 from the GPU path.  All densities stored are lattice-unit MASS densities per
 component (rho_i = M_i rho~_i), in the lattice units of each workload's own
@@ -123,7 +125,28 @@ def serving_pool(n_req=160, seed=5):
     return out
 
 
-def main():
+def ten_co2_states():
+    """Section III.E: the ten-component CO2 mixture at 150 bar; the flash at
+    325 K (flat interface, Table VIII) and the uniform lever-rule densities
+    at 325 K and 400 K (spinodal Cases 1 and 2, Tables IX-X)."""
+    kij = np.array(C.ten_co2_kij())
+    out = {}
+    for T in (325.0, 400.0):
+        st = two_phase_state(C.TEN_CO2, T, 150.0, C.TEN_CO2_Z, kij)
+        st.update(components=comp_list(C.TEN_CO2), T=T, z=list(C.TEN_CO2_Z), kij=kij.tolist())
+        out["ten_co2_%d" % int(T)] = st
+    return out
+
+
+def main(only=None):
+    if only == "ten_co2":
+        with open(Fi.PHASE_STATES) as f:
+            states = json.load(f)
+        states.update(ten_co2_states())
+        with open(Fi.PHASE_STATES, "w") as f:
+            json.dump(states, f, indent=1)
+        print("updated", Fi.PHASE_STATES)
+        return
     states = {}
     # 64x64 three-component droplet: 250 K, 50 bar, z = (0.5, 0.25, 0.25)
     st = two_phase_state(C.DROPLET_3, 250.0, 50.0, [0.5, 0.25, 0.25])
@@ -147,6 +170,7 @@ def main():
                                    instances=ternary_sweep())
     states["serving_pool"] = dict(components=comp_list(C.N_ALKANES),
                                   requests=serving_pool())
+    states.update(ten_co2_states())
     path = Fi.PHASE_STATES
     with open(path, "w") as f:
         json.dump(states, f, indent=1)
@@ -154,4 +178,5 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    # "ten_co2": add / refresh only the ten-component CO2 states
+    main(sys.argv[1] if len(sys.argv) > 1 else None)
