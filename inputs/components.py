@@ -87,3 +87,9 @@ def ten_co2_kij():
     for i in range(n):
         k[i][c] = k[c][i] = TEN_CO2_KIJ_CO2[i]
     return k
+
+
+# Paper, Section III.C: the C1/C2/C3 ternary (k_ij = 0) and its four
+# pressure-temperature cases (bar, K).
+TERNARY_C1_C2_C3 = [TABLE_I["C1"], TABLE_I["C2"], TABLE_I["C3"]]
+TERNARY_CASES = {1: (45.0, 330.0), 2: (48.71, 305.51), 3: (50.0, 250.0), 4: (80.0, 275.0)}

@@ -2,8 +2,8 @@
 workload starts from, computed by the oracle's own flash / Maxwell code.
 
 Run: ``python -m oracle.write_phase_states`` (from the repository root);
-``python -m oracle.write_phase_states ten_co2`` refreshes only the
-ten-component CO2 states.
+``python -m oracle.write_phase_states ten_co2`` (or ``ternary_c1c2c3``)
+refreshes only the ten-component CO2 (or C1/C2/C3 ternary) states.
 Only ``oracle/`` and the seeded draws in ``inputs/`` are used; nothing comes
 from the GPU path.  All densities stored are lattice-unit MASS densities per
 component (rho_i = M_i rho~_i), in the lattice units of each workload's own
@@ -138,11 +138,43 @@ def ten_co2_states():
     return out
 
 
+def ternary_diagram_states(per_case=6, grid=12):
+    """Section III.C: flat-interface states of the C1/C2/C3 ternary at the
+    four (p, T) cases, over overall compositions on a simplex grid (step
+    1/grid); per case the two-phase ones with 0.15 <= S_V <= 0.85 that the
+    stability screen keeps, spread over the grid, at most per_case."""
+    comps = C.TERNARY_C1_C2_C3
+    out = []
+    for case, (p, T) in sorted(C.TERNARY_CASES.items()):
+        cand = []
+        for a in range(1, grid):
+            for b in range(1, grid - a):
+                z = [a / grid, b / grid, (grid - a - b) / grid]
+                st = two_phase_state(comps, T, p, z)
+                if st is None or not (0.15 <= st["S_V"] <= 0.85):
+                    continue
+                cand.append((z, st))
+        step = max(1, len(cand) // per_case)
+        kept = 0
+        for z, st in cand[::step]:
+            if kept >= per_case:
+                break
+            if not stable_in_oracle(comps, T, st["rho_V"], st["rho_L"], st["S_V"], 400):
+                continue
+            st.update(case=case, T=T, p_bar_in=p, z=z)
+            out.append(st)
+            kept += 1
+    return dict(components=comp_list(comps), instances=out)
+
+
 def main(only=None):
-    if only == "ten_co2":
+    if only in ("ten_co2", "ternary_c1c2c3"):
         with open(Fi.PHASE_STATES) as f:
             states = json.load(f)
-        states.update(ten_co2_states())
+        if only == "ten_co2":
+            states.update(ten_co2_states())
+        else:
+            states["ternary_c1c2c3"] = ternary_diagram_states()
         with open(Fi.PHASE_STATES, "w") as f:
             json.dump(states, f, indent=1)
         print("updated", Fi.PHASE_STATES)
@@ -171,6 +203,7 @@ def main(only=None):
     states["serving_pool"] = dict(components=comp_list(C.N_ALKANES),
                                   requests=serving_pool())
     states.update(ten_co2_states())
+    states["ternary_c1c2c3"] = ternary_diagram_states()
     path = Fi.PHASE_STATES
     with open(path, "w") as f:
         json.dump(states, f, indent=1)
@@ -178,5 +211,5 @@ def main(only=None):
 
 
 if __name__ == "__main__":
-    # "ten_co2": add / refresh only the ten-component CO2 states
+    # "ten_co2" / "ternary_c1c2c3": add / refresh only those states
     main(sys.argv[1] if len(sys.argv) > 1 else None)

@@ -7,6 +7,7 @@ thermodynamics (what the paper validates in Section III):
   bulk phases must sit on the flash at the measured p);
 * well-balanced equilibrium: a droplet relaxes to u = 0 to round-off;
 * Young-Laplace (Eq. (14)): Delta p linear in 1 / R_e through ~0;
+* ternary C1/C2/C3 flat interfaces on the flash tie lines (Section III.C);
 * iso-fugacity across a curved interface (Tables IX-X): f_i^L / f_i^V -> 1.
 
 Bulk states are averages over windows of even width: the central-difference
@@ -218,6 +219,38 @@ def test_ternary_sweep_slabs_reach_phase_equilibrium():
     sw.close()
     assert worst_f < 1e-4
     assert worst_p < 1e-2
+
+
+def test_ternary_diagrams_c1_c2_c3_on_flash_tie_lines():
+    """Section III.C: the C1/C2/C3 ternary at its four (p, T) cases, flat
+    interfaces on 400 x 2 slabs started from the flash at (p, T, z) for a
+    spread of overall compositions z, all of them in one batched launch per
+    step (FP64), 10^6 steps as in the paper.  The paper shows the LBM tie
+    lines on the flash phase envelope in ternary diagrams; here every bulk
+    mole fraction must lie within 0.005 of the flash's (bulk = 16-column
+    windows at the vapour edges and the liquid centre)."""
+    capi = _capi()
+    from paper_2306_10652_amd import batch
+    from oracle.lbm import oracle_mixture
+    S = W.states()["ternary_c1c2c3"]
+    comps = [batch._Comp(**c) for c in S["components"]]
+    n = 400
+    specs = [dict(comps=comps, T=i["T"], kij=None, shape=(n, 2),
+                  rho=Fi.slab(n, 2, i["rho_V"], i["rho_L"], i["S_V"])) for i in S["instances"]]
+    sw = batch.Sweep(specs, capi.FP64)
+    sw.step(1000000)
+    worst = {}
+    for sim, inst in zip(sw.sims, S["instances"]):
+        om = oracle_mixture(C.TERNARY_C1_C2_C3, inst["T"])
+        rt = sim.read_moments(velocity=False)["rho"][:, 0, :, :] / om.M[:, None, None]
+        vap = np.concatenate([rt[:, :, 0:8], rt[:, :, n - 8:n]], axis=2).mean(axis=(1, 2))
+        liq = rt[:, :, n // 2 - 8:n // 2 + 8].mean(axis=(1, 2))
+        dx = np.max(np.abs(liq / liq.sum() - np.array(inst["x"])))
+        dy = np.max(np.abs(vap / vap.sum() - np.array(inst["y"])))
+        worst[inst["case"]] = max(worst.get(inst["case"], 0.0), float(dx), float(dy))
+    report("ternary_diagrams", instances=len(specs), worst_dx_by_case=worst)
+    sw.close()
+    assert max(worst.values()) < 0.005
 
 
 def _ten_co2(T):

@@ -190,3 +190,30 @@ def test_alpha_branch_split():
     lo = th.alpha(0.49, 0.5)
     hi = th.alpha(0.4900001, 0.5)
     assert lo != pytest.approx(hi, rel=1e-4)   # a branch switch happens at 0.49
+
+
+def test_stored_ternary_diagram_states_are_tie_lines():
+    """The stored C1/C2/C3 states (Section III.C, four (p, T) cases) are
+    tie lines of the mixture: each phase's density reproduces the case's
+    pressure through Eq. (9), the two phases have equal ln f_i (Eq. (12)),
+    and the overall composition lies on the line between them (lever rule).
+    Checked from the stored densities alone, so a state written with the
+    wrong components, case or pressure fails."""
+    from inputs import fields as Fi
+    st = Fi.load_phase_states()["ternary_c1c2c3"]
+    assert sorted({i["case"] for i in st["instances"]}) == [1, 2, 3, 4]
+    for inst in st["instances"]:
+        p, T = C.TERNARY_CASES[inst["case"]]
+        assert (inst["p_bar_in"], inst["T"]) == (p, T)
+        om = oracle_mixture(C.TERNARY_C1_C2_C3, T)
+        rv = np.array(inst["rho_V"]) / om.M
+        rl = np.array(inst["rho_L"]) / om.M
+        p_lu = om.units.p(p * th.BAR)
+        assert abs(om.pr.pressure_rho(rv) / p_lu - 1) < 1e-9
+        assert abs(om.pr.pressure_rho(rl) / p_lu - 1) < 1e-9
+        np.testing.assert_allclose(om.pr.ln_fugacity_rho(rl), om.pr.ln_fugacity_rho(rv),
+                                   atol=1e-9)
+        x, y, z = rl / rl.sum(), rv / rv.sum(), np.array(inst["z"])
+        beta = inst["beta"]
+        np.testing.assert_allclose(beta * y + (1 - beta) * x, z, atol=1e-9)
+        assert rl.sum() > 1.5 * rv.sum()
