@@ -93,3 +93,18 @@ def ten_co2_kij():
 # pressure-temperature cases (bar, K).
 TERNARY_C1_C2_C3 = [TABLE_I["C1"], TABLE_I["C2"], TABLE_I["C3"]]
 TERNARY_CASES = {1: (45.0, 330.0), 2: (48.71, 305.51), 3: (50.0, 250.0), 4: (80.0, 275.0)}
+
+# Paper, Section III.D: the three-phase C1/C4/CO2 case (Table V constants),
+# k_ij(CO2, C1) = 0.12, k_ij(CO2, C4) = 0.15, the others zero; 225 K, 9 bar,
+# z = (0.0194, 0.2643, 0.7163); lattice anchors R = 1, a_C1 = 0.011550,
+# b_C1 = 0.107781, M_C1 = 1.
+THREE_PHASE = [TABLE_V["C1"], TABLE_V["C4"], TABLE_V["CO2"]]
+THREE_PHASE_Z = [0.0194, 0.2643, 0.7163]
+THREE_PHASE_T_K = 225.0
+THREE_PHASE_P_BAR = 9.0
+THREE_PHASE_A_LU = 0.011550
+THREE_PHASE_B_LU = 0.107781
+
+
+def three_phase_kij():
+    return [[0.0, 0.0, 0.12], [0.0, 0.0, 0.15], [0.12, 0.15, 0.0]]

@@ -36,6 +36,25 @@ def slab(nx, ny, rho_V, rho_L, S_V, W=4.0, nz=1):
     return np.broadcast_to(out[:, None, None, :], (len(rho_V), nz, ny, nx)).copy()
 
 
+def three_phase_slab(nx, ny, rho_V, rho_L1, rho_L2, W=8.0):
+    """Eq. (16): liquid1 | vapour | liquid1 | liquid2 | liquid1 along x with
+    tanh interfaces of width W at S1..S4 = nx/8, 3nx/8, 5nx/8, 7nx/8, one
+    branch per quarter of the box.  The printed fourth branch names S1; the
+    interface it describes sits at S4 (liquid2 -> liquid1 at 7nx/8)."""
+    V, L1, L2 = (np.asarray(r, dtype=np.float64)[:, None] for r in (rho_V, rho_L1, rho_L2))
+    x = np.arange(nx, dtype=np.float64)[None, :]
+
+    def step(a, b, s):          # a for x << s, b for x >> s
+        return 0.5 * (a + b) - 0.5 * (a - b) * np.tanh(2.0 * (x - s) / W)
+
+    q = x <= nx / 4
+    out = np.where(q, step(L1, V, nx / 8), 0.0)
+    out = np.where((x > nx / 4) & (x <= nx / 2), step(V, L1, 3 * nx / 8), out)
+    out = np.where((x > nx / 2) & (x <= 3 * nx / 4), step(L1, L2, 5 * nx / 8), out)
+    out = np.where(x > 3 * nx / 4, step(L2, L1, 7 * nx / 8), out)
+    return np.broadcast_to(out[:, None, None, :], (V.shape[0], 1, ny, nx)).copy()
+
+
 def uniform(nx, ny, rho, nz=1):
     rho = np.asarray(rho, dtype=np.float64)
     return np.broadcast_to(rho[:, None, None, None], (len(rho), nz, ny, nx)).copy()

@@ -19,6 +19,10 @@ Contents, each following the paper's Section II.C unless noted:
                                construction.  The paper uses a flash but does not
                                print its algorithm; these are written from the
                                thermodynamics, not from any listing.
+* ``flash3``                -- the three-phase flash of the three-phase case
+                               (Section III.D): multiphase Rachford-Rice and
+                               successive substitution, written from the same
+                               thermodynamics (the paper used an external code).
 """
 import math
 from dataclasses import dataclass
@@ -255,6 +259,81 @@ def flash(mix, z, p, K0=None, tol=1e-13, maxit=20000):
     rhoV = p / (ZV * mix.RT)
     return FlashResult(beta if beta is not None else float("nan"), x, y, ZL, ZV,
                        rhoL, rhoV, it, converged, bool(two))
+
+
+@dataclass
+class Flash3Result:
+    beta: np.ndarray      # phase mole fractions, in the order of the guesses
+    x: np.ndarray         # [3][N] phase compositions
+    Z: np.ndarray         # compressibility factor of each phase
+    rho: np.ndarray       # molar density of each phase
+    iterations: int
+    converged: bool
+
+
+def multiphase_rachford_rice(z, K, beta0, tol=1e-15, maxit=200):
+    """Phase fractions of a multiphase split with K_ik = x_ik / x_i0 (phase 0
+    the reference, K_i0 = 1): the zeros of
+        h_k(beta) = sum_i z_i (K_ik - 1) / E_i,  E_i = 1 + sum_{k>0} beta_k (K_ik - 1),
+    k > 0, i.e. sum_i x_ik = sum_i x_i0 (with x_ik = z_i K_ik / E_i).  Newton
+    on the k > 0 fractions with the analytic Jacobian
+        dh_k / dbeta_l = -sum_i z_i (K_ik - 1)(K_il - 1) / E_i^2,
+    halving a step that would make some E_i non-positive."""
+    z = np.asarray(z, dtype=np.float64)
+    km1 = np.asarray(K, dtype=np.float64)[:, 1:] - 1.0          # [N][P-1]
+    b = np.asarray(beta0, dtype=np.float64)[1:].copy()
+    for _ in range(maxit):
+        E = 1.0 + km1 @ b
+        h = (z / E) @ km1
+        J = -(km1 * (z / (E * E))[:, None]).T @ km1
+        step = np.linalg.solve(J, -h)
+        t = 1.0
+        while np.any(1.0 + km1 @ (b + t * step) <= 0.0):
+            t *= 0.5
+        b = b + t * step
+        if np.max(np.abs(t * step)) < tol:
+            break
+    return np.concatenate([[1.0 - b.sum()], b])
+
+
+def flash3(mix, z, p, x0, labels, tol=1e-12, maxit=5000):
+    """Isothermal three-phase flash at (T, p, z) by successive substitution
+    on the K-values relative to phase 0 (the textbook multiphase extension
+    of the two-phase flash above).
+
+    x0: [3][N] initial compositions; labels: "V" or "L" per phase, which
+    picks the largest or the smallest cubic root for that phase.  Each
+    iteration: multiphase Rachford-Rice for the phase fractions, phase
+    compositions from the mass balance, ln K_ik = ln phi_i0 - ln phi_ik.
+    Stops when max |delta ln K| < tol.  At fixed T and p a three-component
+    three-phase state has no free intensive variable (phase rule), so the
+    compositions found do not depend on z inside the three-phase region."""
+    z = np.asarray(z, dtype=np.float64)
+    z = z / z.sum()
+    x0 = np.asarray(x0, dtype=np.float64)
+    lnK = np.log(x0 / x0[0])                 # [3][N]
+    beta = np.full(3, 1.0 / 3.0)
+    converged = False
+    it = 0
+    X = x0.copy()
+    Z = np.zeros(3)
+    for it in range(1, maxit + 1):
+        K = np.exp(lnK).T                    # [N][3]
+        beta = multiphase_rachford_rice(z, K, beta)
+        E = K @ beta
+        X = (z[:, None] * K / E[:, None]).T
+        X = X / X.sum(axis=1, keepdims=True)
+        lnphi = np.zeros((3, mix.N))
+        for k in range(3):
+            Z[k], lnphi[k] = mix.phase(X[k], p, labels[k])
+        new = lnphi[0][None, :] - lnphi
+        d = np.max(np.abs(new - lnK))
+        lnK = new
+        if d < tol:
+            converged = True
+            break
+    rho = p / (Z * mix.RT)
+    return Flash3Result(beta, X, Z.copy(), rho, it, converged)
 
 
 def maxwell(mix, p0=None, tol=1e-14, maxit=200):

@@ -2,12 +2,13 @@
 workload starts from, computed by the oracle's own flash / Maxwell code.
 
 Run: ``python -m oracle.write_phase_states`` (from the repository root);
-``python -m oracle.write_phase_states ten_co2`` (or ``ternary_c1c2c3``)
-refreshes only the ten-component CO2 (or C1/C2/C3 ternary) states.
+``python -m oracle.write_phase_states ten_co2`` (or ``ternary_c1c2c3``, or
+``three_phase``) refreshes only that group of states.
 Only ``oracle/`` and the seeded draws in ``inputs/`` are used; nothing comes
 from the GPU path.  All densities stored are lattice-unit MASS densities per
 component (rho_i = M_i rho~_i), in the lattice units of each workload's own
-anchor (its first component, a = 2/49, b = 2/21, R = 1, M = 1).
+anchor (its first component, a = 2/49, b = 2/21, R = 1, M = 1; the three-phase
+case uses its own anchors, stored with it).
 """
 import json
 import os
@@ -167,14 +168,38 @@ def ternary_diagram_states(per_case=6, grid=12):
     return dict(components=comp_list(comps), instances=out)
 
 
+def three_phase_state():
+    """Section III.D: the C1/C4/CO2 three-phase flash at 225 K and 9 bar in
+    the lattice units of the Table V anchors; phases in order vapour,
+    liquid1, liquid2 (increasing mass density)."""
+    comps = C.THREE_PHASE
+    om = oracle_mixture(comps, C.THREE_PHASE_T_K, np.array(C.three_phase_kij()),
+                        a_lu=C.THREE_PHASE_A_LU, b_lu=C.THREE_PHASE_B_LU)
+    p_lu = om.units.p(C.THREE_PHASE_P_BAR * th.BAR)
+    x0 = [[0.3, 0.02, 0.68], [0.01, 0.6, 0.39], [0.01, 0.1, 0.89]]
+    r = th.flash3(om.pr, C.THREE_PHASE_Z, p_lu, x0, "VLL")
+    assert r.converged
+    S = r.beta / r.rho
+    rho = [list(om.M * r.x[k] * r.rho[k]) for k in range(3)]
+    return dict(components=comp_list(comps), T=C.THREE_PHASE_T_K,
+                p_bar=C.THREE_PHASE_P_BAR, p_lu=p_lu, z=list(C.THREE_PHASE_Z),
+                kij=C.three_phase_kij(), a_lu=C.THREE_PHASE_A_LU, b_lu=C.THREE_PHASE_B_LU,
+                beta=list(r.beta), S=list(S / S.sum()), x=[list(v) for v in r.x],
+                rho_V=rho[0], rho_L1=rho[1], rho_L2=rho[2])
+
+
+PARTIAL = {"ten_co2": lambda st: st.update(ten_co2_states()),
+           "ternary_c1c2c3": lambda st: st.update(ternary_c1c2c3=ternary_diagram_states()),
+           "three_phase": lambda st: st.update(three_phase=three_phase_state())}
+
+
 def main(only=None):
-    if only in ("ten_co2", "ternary_c1c2c3"):
+    if only is not None:
+        if only not in PARTIAL:
+            raise SystemExit("unknown state group %r (known: %s)" % (only, ", ".join(PARTIAL)))
         with open(Fi.PHASE_STATES) as f:
             states = json.load(f)
-        if only == "ten_co2":
-            states.update(ten_co2_states())
-        else:
-            states["ternary_c1c2c3"] = ternary_diagram_states()
+        PARTIAL[only](states)
         with open(Fi.PHASE_STATES, "w") as f:
             json.dump(states, f, indent=1)
         print("updated", Fi.PHASE_STATES)
@@ -204,6 +229,7 @@ def main(only=None):
                                   requests=serving_pool())
     states.update(ten_co2_states())
     states["ternary_c1c2c3"] = ternary_diagram_states()
+    states["three_phase"] = three_phase_state()
     path = Fi.PHASE_STATES
     with open(path, "w") as f:
         json.dump(states, f, indent=1)
@@ -211,5 +237,5 @@ def main(only=None):
 
 
 if __name__ == "__main__":
-    # "ten_co2" / "ternary_c1c2c3": add / refresh only those states
+    # a group name (see PARTIAL): add / refresh only that group
     main(sys.argv[1] if len(sys.argv) > 1 else None)

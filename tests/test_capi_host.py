@@ -54,6 +54,20 @@ def test_lattice_constants_match_oracle_units(comps, T, kij_seed):
                                atol=0)
 
 
+def test_lattice_constants_with_other_anchors_match_oracle():
+    """The three-phase case's own anchors (Section III.D: a_C1 = 0.011550,
+    b_C1 = 0.107781, R = 1) and k_ij: the library and the oracle agree."""
+    capi = _capi()
+    from oracle.lbm import oracle_mixture
+    kij = np.array(C.three_phase_kij())
+    mix = capi.Mixture.from_components(C.THREE_PHASE, C.THREE_PHASE_T_K, kij,
+                                       a_ref=C.THREE_PHASE_A_LU, b_ref=C.THREE_PHASE_B_LU)
+    om = oracle_mixture(C.THREE_PHASE, C.THREE_PHASE_T_K, kij, a_lu=C.THREE_PHASE_A_LU,
+                        b_lu=C.THREE_PHASE_B_LU)
+    np.testing.assert_allclose(mix.lattice_constants(), om.lattice_constants(), rtol=1e-13,
+                               atol=0)
+
+
 def test_mixture_argument_validation():
     capi = _capi()
     c = C.DROPLET_3

@@ -217,3 +217,54 @@ def test_stored_ternary_diagram_states_are_tie_lines():
         beta = inst["beta"]
         np.testing.assert_allclose(beta * y + (1 - beta) * x, z, atol=1e-9)
         assert rl.sum() > 1.5 * rv.sum()
+
+
+def _three_phase_si():
+    comps = C.THREE_PHASE
+    mix = th.si_mixture(comps, C.THREE_PHASE_T_K, C.three_phase_kij())
+    x0 = [[0.3, 0.02, 0.68], [0.01, 0.6, 0.39], [0.01, 0.1, 0.89]]   # V, C4-rich, CO2-rich
+    p = C.THREE_PHASE_P_BAR * th.BAR
+    return mix, p, x0, th.flash3(mix, C.THREE_PHASE_Z, p, x0, "VLL")
+
+
+def test_three_phase_flash_saturations_of_section_iii_d():
+    """Section III.D: at 225 K, 9 bar and the printed z the C1/C4/CO2
+    mixture (Table V, k_ij 0.12 / 0.15) splits into vapour, liquid1 and
+    liquid2 with volume fractions 0.25, 0.5 and 0.25 (the paper's flash;
+    the slab of Eq. (16) is built on them), in order of increasing mass
+    density."""
+    mix, p, _, r = _three_phase_si()
+    assert r.converged and np.all(r.beta > 0)
+    S = r.beta / r.rho
+    S = S / S.sum()
+    np.testing.assert_allclose(S, [0.25, 0.5, 0.25], atol=5e-3)
+    M = np.array([c.M for c in C.THREE_PHASE])
+    mass = [float(r.x[k] @ M * r.rho[k]) for k in range(3)]
+    assert mass[0] < mass[1] < mass[2]
+    np.testing.assert_allclose(r.beta @ r.x, C.THREE_PHASE_Z, atol=1e-12)
+
+
+def test_three_phase_flash_pairs_are_two_phase_tie_lines():
+    """Every pair of coexisting phases is itself a two-phase equilibrium:
+    the two-phase flash (pinned to Table III) fed with the pair's midpoint
+    returns the pair.  Vapour-liquid1 and vapour-liquid2 are checked, which
+    makes liquid1-liquid2 iso-fugacity follow."""
+    mix, p, _, r = _three_phase_si()
+    for a in (1, 2):
+        f = th.flash(mix, 0.5 * (r.x[a] + r.x[0]), p, K0=r.x[0] / r.x[a])
+        assert f.two_phase
+        np.testing.assert_allclose(f.x, r.x[a], atol=1e-10)
+        np.testing.assert_allclose(f.y, r.x[0], atol=1e-10)
+        assert abs(f.beta - 0.5) < 1e-10
+
+
+def test_three_phase_flash_phase_rule():
+    """Three components in three phases at fixed T and p have no free
+    intensive variable: another overall composition inside the three-phase
+    triangle gives the same phases, in the amounts that make it up."""
+    mix, p, x0, r = _three_phase_si()
+    w = np.array([0.2, 0.3, 0.5])
+    q = th.flash3(mix, w @ r.x, p, x0, "VLL")
+    assert q.converged
+    np.testing.assert_allclose(q.x, r.x, atol=1e-10)
+    np.testing.assert_allclose(q.beta, w, atol=1e-10)
