@@ -41,7 +41,10 @@ class OracleParams(ctypes.Structure):
                 ("rho_c", ctypes.c_double),
                 ("b", ctypes.c_double * MAXC), ("M", ctypes.c_double * MAXC),
                 ("sqk", ctypes.c_double * MAXC),
-                ("aij", ctypes.c_double * (MAXC * MAXC))]
+                ("aij", ctypes.c_double * (MAXC * MAXC)),
+                ("eos", ctypes.c_int), ("d1", ctypes.c_double), ("d2", ctypes.c_double)]
+
+EOS_CODE = {"PR": 0, "SRK": 1, "vdW": 2}
 
 
 _lib = None
@@ -93,7 +96,7 @@ class OracleMixture:
     """A mixture in lattice units, as the oracle sees it."""
     comps: list
     units: thermo.LatticeUnits
-    pr: thermo.PRMixture        # lattice-unit PR mixture
+    pr: thermo.PRMixture        # lattice-unit cubic-EOS mixture (PR unless eos says otherwise)
     M: np.ndarray               # lattice molar masses
     sqk: np.ndarray             # sqrt(kappa_i)
     tau: float
@@ -118,8 +121,10 @@ class OracleMixture:
 
 
 def oracle_mixture(comps, T_K, kij=None, ref=0, kappa_ref=0.02, a_lu=2.0 / 49.0,
-                   b_lu=2.0 / 21.0, R_lu=1.0, tau=1.0):
-    units = thermo.LatticeUnits(comps[ref], a_lu, b_lu, R_lu)
+                   b_lu=2.0 / 21.0, R_lu=1.0, tau=1.0, eos="PR"):
+    """The paper's anchors (a_ref = 2/49, b_ref = 2/21, R = 1) by default,
+    for every EOS."""
+    units = thermo.LatticeUnits(comps[ref], a_lu, b_lu, R_lu, eos=eos)
     pr = units.mixture(comps, T_K, kij)
     M = units.molar_masses(comps)
     kappa = kappa_ref * pr.a / pr.a[ref]          # Eq. (6)-(8)
@@ -134,6 +139,8 @@ def make_params(mix, lattice, nx, ny, nz=1, rho_c=0.0):
     P.tau = mix.tau
     P.RT = mix.RT
     P.rho_c = rho_c
+    P.eos = EOS_CODE[mix.pr.eos]
+    P.d1, P.d2 = mix.pr.d1, mix.pr.d2
     for i in range(mix.N):
         P.b[i] = mix.pr.b[i]
         P.M[i] = mix.M[i]

@@ -43,6 +43,8 @@ typedef struct {
     double M[OR_MAXC];      /* molar masses, lattice units */
     double sqk[OR_MAXC];    /* sqrt(kappa_i) */
     double aij[OR_MAXC * OR_MAXC]; /* (a alpha)_ij = sqrt(aa_i aa_j)(1 - k_ij) */
+    int eos;                /* 0 = Peng-Robinson (the paper's), 1 = SRK, 2 = vdW */
+    double d1, d2;          /* p = RT/(v-b) - a alpha/((v + d1 b)(v + d2 b)) */
 } oracle_params;
 
 /* ---- velocity sets ------------------------------------------------------ */
@@ -131,14 +133,19 @@ void oracle_forcing(int lattice, const double *F, const double *G,
     }
 }
 
-/* ---- Eq. (9)-(12): PR pressure and ln f_i ------------------------------ */
+/* ---- Eq. (9)-(12): cubic-EOS pressure and ln f_i ---------------------- */
 /* Eq. (12) as printed contains ln(x_i p) and ln((v - b_m) p / RT), which are
  * undefined where p <= 0 (inside interfaces).  Their sum is
- * ln(rt_i RT / (1 - b_m rt)), so the oracle evaluates
+ * ln(rt_i RT / (1 - b_m rt)), so the oracle evaluates, for the cubic
+ * p = RT/(v - b_m) - a_m / ((v + d1 b_m)(v + d2 b_m))  (PR: Eq. (9)),
  *   ln f_i = ln(rt_i RT/(1 - eta)) + (b_i/b_m)(Z - 1)
- *            - (a_m / (2 sqrt2 b_m RT)) (2 S_i / a_m - b_i / b_m)
- *              ln[(1 + (1+sqrt2) eta) / (1 + (1-sqrt2) eta)],
- * eta = b_m rt, Z = p / (rt RT), S_i = sum_j x_j (a alpha)_ij.
+ *            - (a_m / (b_m RT)) (2 S_i / a_m - b_i / b_m) Lam,
+ *   Lam = ln[(1 + d1 eta) / (1 + d2 eta)] / (d1 - d2)   (PR, SRK),
+ *   Lam = eta                                           (vdW, d1 = d2 = 0:
+ *         the limit, which gives b_i rt/(1 - eta) - 2 S_i rt / RT for the
+ *         non-logarithmic terms, the textbook vdW expression),
+ * eta = b_m rt, Z = p / (rt RT), S_i = sum_j x_j (a alpha)_ij.  For PR,
+ * d1 - d2 = 2 sqrt2 and this is Eq. (12) term by term.
  * Returns status bits: 2 if 1 - eta <= 0, 4 if some rt_i <= 0.            */
 int oracle_ln_fugacity(const oracle_params *P, const double *rt_i, double *lnf,
                        double *p_out) {
@@ -161,13 +168,14 @@ int oracle_ln_fugacity(const oracle_params *P, const double *rt_i, double *lnf,
     }
     double eta = bm * rt;
     if (!(1.0 - eta > 0.0)) st |= 2;
-    double p = rt * P->RT / (1.0 - eta) - am * rt * rt / (1.0 + 2.0 * eta - eta * eta);
+    double p = rt * P->RT / (1.0 - eta)
+             - am * rt * rt / ((1.0 + P->d1 * eta) * (1.0 + P->d2 * eta));
     double Z = p / (rt * P->RT);
-    double s2 = sqrt(2.0);
-    double Lam = log((1.0 + (1.0 + s2) * eta) / (1.0 + (1.0 - s2) * eta));
+    double Lam = P->eos == 2 ? eta
+               : log((1.0 + P->d1 * eta) / (1.0 + P->d2 * eta)) / (P->d1 - P->d2);
     for (int i = 0; i < N; ++i) {
         lnf[i] = log(rt_i[i] * P->RT / (1.0 - eta)) + P->b[i] / bm * (Z - 1.0)
-               - am / (2.0 * s2 * bm * P->RT) * (2.0 * S[i] / am - P->b[i] / bm) * Lam;
+               - am / (bm * P->RT) * (2.0 * S[i] / am - P->b[i] / bm) * Lam;
     }
     if (p_out) *p_out = p;
     return st;

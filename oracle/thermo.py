@@ -7,10 +7,12 @@ never does, and this module shares no code with it.
 Contents, each following the paper's Section II.C unless noted:
 
 * ``alpha``                 -- the alpha(omega, T_r) correlation (two branches,
-                               split at omega = 0.49).
+                               split at omega = 0.49); Soave's for SRK.
 * ``PRMixture``             -- a_i, b_i, alpha_i, vdW mixing rules Eq. (10)-(11),
                                pressure Eq. (9), the cubic in Z obtained from
-                               Eq. (9), ln phi_i exactly as printed in Eq. (12).
+                               Eq. (9), ln phi_i exactly as printed in Eq. (12);
+                               with ``eos="SRK"`` or ``"vdW"`` the same for those
+                               cubics (table ``EOS``).
 * ``LatticeUnits``          -- conversion to lattice units by fixing R, a, b and M
                                of a reference component (Section III.A).
 * ``flash`` / ``maxwell``   -- textbook two-phase flash (Wilson start,
@@ -36,26 +38,48 @@ BAR = 1.0e5                    # Pa
 SQRT2 = math.sqrt(2.0)
 
 
-def alpha(omega, Tr):
-    """alpha_i(T) of Section II.C: first branch for omega <= 0.49."""
+# The cubic equations of state the oracle knows, written
+#     p = RT / (v - b) - (a alpha) / ((v + d1 b)(v + d2 b)),
+# with the prefactors of a = Omega_a R^2 Tc^2 / pc and b = Omega_b R Tc / pc
+# that put the critical point at (Tc, pc).  PR is the paper's (Section II.C);
+# Soave-Redlich-Kwong and van der Waals are the textbook alternatives the
+# fugacity formulation admits unchanged (Section I: any multicomponent EOS).
+_CBRT2 = 2.0 ** (1.0 / 3.0)
+EOS = {
+    "PR": dict(d1=1.0 + SQRT2, d2=1.0 - SQRT2, omega_a=OMEGA_A, omega_b=OMEGA_B),
+    "SRK": dict(d1=1.0, d2=0.0, omega_a=1.0 / (9.0 * (_CBRT2 - 1.0)),
+                omega_b=(_CBRT2 - 1.0) / 3.0),
+    "vdW": dict(d1=0.0, d2=0.0, omega_a=27.0 / 64.0, omega_b=1.0 / 8.0),
+}
+
+
+def alpha(omega, Tr, eos="PR"):
+    """alpha_i(T).  PR: the correlation of Section II.C, first branch for
+    omega <= 0.49.  SRK: Soave's m = 0.480 + 1.574 w - 0.176 w^2.  vdW: 1."""
     omega = np.asarray(omega, dtype=np.float64)
     Tr = np.asarray(Tr, dtype=np.float64)
-    m_low = 0.374640 + 1.54226 * omega - 0.26992 * omega ** 2
-    m_high = (0.379642 + 1.48503 * omega - 0.164423 * omega ** 2
-              + 0.016666 * omega ** 3)
-    m = np.where(omega <= 0.49, m_low, m_high)
+    if eos == "vdW":
+        return np.ones(np.broadcast(omega, Tr).shape)
+    if eos == "SRK":
+        m = 0.480 + 1.574 * omega - 0.176 * omega ** 2
+    else:
+        m_low = 0.374640 + 1.54226 * omega - 0.26992 * omega ** 2
+        m_high = (0.379642 + 1.48503 * omega - 0.164423 * omega ** 2
+                  + 0.016666 * omega ** 3)
+        m = np.where(omega <= 0.49, m_low, m_high)
     return (1.0 + m * (1.0 - np.sqrt(Tr))) ** 2
 
 
 class PRMixture:
-    """Peng-Robinson mixture at a fixed temperature, in any consistent units.
+    """Cubic-EOS mixture at a fixed temperature, in any consistent units;
+    Peng-Robinson (the paper's) unless ``eos`` names SRK or vdW.
 
     Parameters are per-component critical constants expressed in the same
     unit system as ``R`` and ``T`` (SI by default).  ``kij`` is the binary
     interaction matrix (the paper writes it delta_ij, Eq. (10)).
     """
 
-    def __init__(self, Tc, pc, omega, T, kij=None, R=R_SI):
+    def __init__(self, Tc, pc, omega, T, kij=None, R=R_SI, eos="PR"):
         self.Tc = np.asarray(Tc, dtype=np.float64)
         self.pc = np.asarray(pc, dtype=np.float64)
         self.omega = np.asarray(omega, dtype=np.float64)
@@ -63,9 +87,12 @@ class PRMixture:
         self.T = float(T)
         self.R = float(R)
         self.RT = self.R * self.T
-        self.a = OMEGA_A * self.R ** 2 * self.Tc ** 2 / self.pc
-        self.b = OMEGA_B * self.R * self.Tc / self.pc
-        self.alpha = alpha(self.omega, self.T / self.Tc)
+        self.eos = eos
+        e = EOS[eos]
+        self.d1, self.d2 = e["d1"], e["d2"]
+        self.a = e["omega_a"] * self.R ** 2 * self.Tc ** 2 / self.pc
+        self.b = e["omega_b"] * self.R * self.Tc / self.pc
+        self.alpha = alpha(self.omega, self.T / self.Tc, eos)
         self.aalpha = self.a * self.alpha
         k = np.zeros((self.N, self.N)) if kij is None else np.asarray(kij, dtype=np.float64)
         self.kij = k
@@ -83,9 +110,10 @@ class PRMixture:
 
     # -- Eq. (9) ----------------------------------------------------------
     def pressure(self, x, v):
-        """p = RT/(v - b_m) - (a alpha)_m / (v^2 + 2 b_m v - b_m^2)."""
+        """p = RT/(v - b_m) - (a alpha)_m / ((v + d1 b_m)(v + d2 b_m));
+        for PR the denominator is v^2 + 2 b_m v - b_m^2 (Eq. (9))."""
         bm, am, _ = self.mix(x)
-        return self.RT / (v - bm) - am / (v * v + 2.0 * bm * v - bm * bm)
+        return self.RT / (v - bm) - am / ((v + self.d1 * bm) * (v + self.d2 * bm))
 
     def pressure_rho(self, rho_molar):
         """Pressure from a vector of component molar densities."""
@@ -99,13 +127,19 @@ class PRMixture:
         return am * p / self.RT ** 2, bm * p / self.RT
 
     def z_roots(self, x, p):
-        """Real roots Z > B of Eq. (9) rewritten with v = Z RT / p, ascending.
+        """Real roots Z > B of the EOS rewritten with v = Z RT / p, ascending:
+        with u = d1 + d2, w = d1 d2,
 
-        Z^3 - (1 - B) Z^2 + (A - 3B^2 - 2B) Z - (AB - B^2 - B^3) = 0.
-        Each root is polished by Newton steps on the same polynomial.
+        Z^3 - (1 + B - uB) Z^2 + (A + wB^2 - uB - uB^2) Z - (AB + wB^2 + wB^3) = 0,
+
+        for PR (u = 2, w = -1) Z^3 - (1 - B) Z^2 + (A - 3B^2 - 2B) Z -
+        (AB - B^2 - B^3) = 0.  Each root is polished by Newton steps on the
+        same polynomial.
         """
         A, B = self.AB(x, p)
-        c = [1.0, -(1.0 - B), A - 3.0 * B * B - 2.0 * B, -(A * B - B * B - B ** 3)]
+        u, w = self.d1 + self.d2, self.d1 * self.d2
+        c = [1.0, -(1.0 + B - u * B), A + w * B * B - u * B - u * B * B,
+             -(A * B + w * B * B + w * B ** 3)]
         r = np.roots(c)
         out = []
         for z in r:
@@ -124,15 +158,27 @@ class PRMixture:
 
     # -- Eq. (12) -----------------------------------------------------------
     def ln_phi(self, x, Z, p):
-        """ln(f_i / (x_i p)) exactly in the printed form of Eq. (12)."""
+        """ln(f_i / (x_i p)).  PR: exactly the printed form of Eq. (12).
+        SRK: the same form with its own d1, d2,
+            (b_i/b_m)(Z - 1) - ln(Z - B)
+            - A / (B (d1 - d2)) (2 S_i / a_m - b_i / b_m) ln[(Z + d1 B)/(Z + d2 B)].
+        vdW (d1 = d2 = 0), the textbook expression
+            b_i / (v - b_m) - ln(Z - B) - 2 S_i / (RT v)."""
         x = np.asarray(x, dtype=np.float64)
         bm, am, S = self.mix(x)
         v = Z * self.RT / p
-        term1 = self.b / bm * (p * v / self.RT - 1.0)
         term2 = -math.log((v - bm) * p / self.RT)
-        coef = am / (2.0 * SQRT2 * bm * self.RT)
+        if self.eos == "vdW":
+            return self.b / (v - bm) + term2 - 2.0 * S / (self.RT * v)
+        term1 = self.b / bm * (p * v / self.RT - 1.0)
+        if self.eos == "PR":
+            coef = am / (2.0 * SQRT2 * bm * self.RT)
+            bracket = self.b / bm - 2.0 / am * S
+            lnr = math.log((v + (1.0 + SQRT2) * bm) / (v + (1.0 - SQRT2) * bm))
+            return term1 + term2 + coef * bracket * lnr
+        coef = am / ((self.d1 - self.d2) * bm * self.RT)
         bracket = self.b / bm - 2.0 / am * S
-        lnr = math.log((v + (1.0 + SQRT2) * bm) / (v + (1.0 - SQRT2) * bm))
+        lnr = math.log((v + self.d1 * bm) / (v + self.d2 * bm))
         return term1 + term2 + coef * bracket * lnr
 
     def ln_fugacity(self, x, Z, p):
@@ -390,14 +436,16 @@ class LatticeUnits:
     a = Omega_a R^2 Tc^2 / pc and b = Omega_b R Tc / pc.
     """
 
-    def __init__(self, ref, a_lu=2.0 / 49.0, b_lu=2.0 / 21.0, R_lu=1.0, M_lu=1.0):
+    def __init__(self, ref, a_lu=2.0 / 49.0, b_lu=2.0 / 21.0, R_lu=1.0, M_lu=1.0, eos="PR"):
         self.ref = ref
+        self.eos = eos
+        oa, ob = EOS[eos]["omega_a"], EOS[eos]["omega_b"]
         self.a_lu, self.b_lu, self.R_lu, self.M_lu = a_lu, b_lu, R_lu, M_lu
-        self.Tc_ref_lu = (a_lu / b_lu) * (OMEGA_B / OMEGA_A) / R_lu
-        self.pc_ref_lu = OMEGA_B * R_lu * self.Tc_ref_lu / b_lu
+        self.Tc_ref_lu = (a_lu / b_lu) * (ob / oa) / R_lu
+        self.pc_ref_lu = ob * R_lu * self.Tc_ref_lu / b_lu
         self.T_scale = ref.Tc / self.Tc_ref_lu                 # K per lu
         self.p_scale = ref.pc * BAR / self.pc_ref_lu            # Pa per lu
-        b_ref_si = OMEGA_B * R_SI * ref.Tc / (ref.pc * BAR)
+        b_ref_si = ob * R_SI * ref.Tc / (ref.pc * BAR)
         self.V_scale = b_ref_si / b_lu                          # m^3/mol per lu
         self.M_scale = ref.M / M_lu                             # g/mol per lu
 
@@ -419,16 +467,16 @@ class LatticeUnits:
         Tc = np.array([c.Tc for c in comps]) / self.T_scale
         pc = np.array([c.pc * BAR for c in comps]) / self.p_scale
         om = np.array([c.omega for c in comps])
-        return PRMixture(Tc, pc, om, self.T(T_K), kij, R=self.R_lu)
+        return PRMixture(Tc, pc, om, self.T(T_K), kij, R=self.R_lu, eos=self.eos)
 
     def molar_masses(self, comps):
         return np.array([c.M for c in comps]) / self.M_scale
 
 
-def si_mixture(comps, T_K, kij=None):
-    """The PR mixture in SI units (Pa, m^3/mol)."""
+def si_mixture(comps, T_K, kij=None, eos="PR"):
+    """The cubic-EOS mixture in SI units (Pa, m^3/mol)."""
     return PRMixture([c.Tc for c in comps], [c.pc * BAR for c in comps],
-                     [c.omega for c in comps], T_K, kij)
+                     [c.omega for c in comps], T_K, kij, eos=eos)
 
 
 def mass_density_si(comps, rho_molar_si_vec):

@@ -187,6 +187,24 @@ def test_flat_interface_relaxes_to_maxwell(oracle_lib):
     assert np.abs(fl["u"]).max() < 1e-9
 
 
+@pytest.mark.parametrize("eos", ["SRK", "vdW"])
+def test_flat_interface_relaxes_to_maxwell_other_cubics(oracle_lib, eos):
+    """The same C1 slab (177.24 K, the paper's anchors) with the SRK or vdW
+    equation of state in place of PR: the bulk densities (even windows)
+    reach that EOS's own Maxwell densities and u decays to round-off."""
+    c1 = C.TABLE_I["C1"]
+    mix = lbm.oracle_mixture([c1], 177.24, eos=eos)
+    ps, rV, rL = th.maxwell(mix.pr)
+    f = Fi.slab(128, 1, [0.98 * rV], [1.02 * rL], 0.5)
+    sim = lbm.OracleLBM(mix, 0, (128, 1), f)
+    sim.run(20000)
+    fl = sim.fields()
+    rt = fl["rho"][0, 0, 0] / mix.M[0]
+    assert abs(rt[0:4].mean() / rV - 1) < 2e-5
+    assert abs(rt[62:66].mean() / rL - 1) < 2e-5
+    assert np.abs(fl["u"]).max() < 1e-9
+
+
 def test_d3q19_reduces_to_d2q9_on_a_one_dimensional_field(oracle_lib):
     """A field that varies along x only: D2Q9 and D3Q19 both reduce to the
     same three-velocity lattice along x (weights 2/3, 1/6, 1/6; the same
