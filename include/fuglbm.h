@@ -62,6 +62,16 @@ typedef enum {
 typedef enum { FUGLBM_D2Q9 = 0, FUGLBM_D3Q19 = 1 } fuglbm_lattice;
 typedef enum { FUGLBM_FP64 = 0, FUGLBM_FP32_STORAGE = 1 } fuglbm_precision;
 
+/* Cubic equation of state p = RT/(v - b) - a alpha / ((v + d1 b)(v + d2 b)).
+ * PR is the paper's (Section II.C, Eq. (9)-(12)): d1,2 = 1 +- sqrt2,
+ * a = 0.457235529 R^2 Tc^2/pc, b = 0.077796074 R Tc/pc, alpha of Section II.C.
+ * SRK: d1 = 1, d2 = 0, a = R^2 Tc^2 / (9 (2^(1/3) - 1) pc),
+ * b = (2^(1/3) - 1) R Tc / (3 pc), Soave's alpha (m = 0.480 + 1.574 w - 0.176 w^2).
+ * vdW: d1 = d2 = 0, a = 27 R^2 Tc^2 / (64 pc), b = R Tc / (8 pc), alpha = 1.
+ * The method takes any of them unchanged (Section I); only ln f_i and the
+ * pressure differ. */
+typedef enum { FUGLBM_EOS_PR = 0, FUGLBM_EOS_SRK = 1, FUGLBM_EOS_VDW = 2 } fuglbm_eos;
+
 /* Device status bits (fuglbm_diag.status). */
 #define FUGLBM_ST_NONFINITE 1u   /* a non-finite ln f_i, density or population */
 #define FUGLBM_ST_COVOLUME  2u   /* 1 - b_m rt <= 0 (outside the EOS domain) */
@@ -87,6 +97,7 @@ typedef struct {
     double a_ref_lu, b_ref_lu, R_lu; /* 0 = defaults 2/49, 2/21, 1 */
     double kappa_ref_lu;           /* kappa of the reference component, lattice units */
     double tau;                    /* BGK relaxation time, > 1/2 (paper: 1) */
+    int32_t eos;                   /* fuglbm_eos; 0 (a zeroed descriptor) = PR */
 } fuglbm_mixture_desc;
 
 /* Diagnostics (FP64 sums in a fixed order: bitwise reproducible). */
@@ -102,8 +113,11 @@ typedef struct {
 
 /* Build a mixture: unit conversion and every per-component constant in
  * FP64 (a_i, b_i, alpha_i(T), (a alpha)_ij, sqrt kappa_i, M_i).
+ * The lattice-unit anchors a_ref_lu, b_ref_lu are those of the chosen EOS's
+ * a and b (defaults 2/49, 2/21 for every EOS).
  * Errors: EINVAL for null/out-of-range fields, non-positive Tc/pc/M/T,
- * tau <= 1/2, asymmetric kij or a non-zero kij diagonal; ENOMEM. */
+ * tau <= 1/2, asymmetric kij or a non-zero kij diagonal, an unknown eos;
+ * ENOMEM. */
 fuglbm_status fuglbm_init_mixture(const fuglbm_mixture_desc *desc, fuglbm_mixture **out);
 
 /* Copy the lattice-unit constants into host array out[n]:

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libfuglbm.so")
 FUGLBM_MAX_COMP = 16
 D2Q9, D3Q19 = 0, 1
 FP64, FP32_STORAGE = 0, 1
+EOS_PR, EOS_SRK, EOS_VDW = 0, 1, 2
+EOS_CODES = {"PR": EOS_PR, "SRK": EOS_SRK, "vdW": EOS_VDW}
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNPHYSICAL",
                 5: "ENONFINITE", 6: "ESTATE"}
 
@@ -47,7 +49,8 @@ class MixtureDesc(ctypes.Structure):
                 ("a_ref_lu", ctypes.c_double), ("b_ref_lu", ctypes.c_double),
                 ("R_lu", ctypes.c_double),
                 ("kappa_ref_lu", ctypes.c_double),
-                ("tau", ctypes.c_double)]
+                ("tau", ctypes.c_double),
+                ("eos", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):
@@ -130,7 +133,7 @@ class Mixture:
     """Owner of a ``fuglbm_mixture`` handle (physical constants in)."""
 
     def __init__(self, Tc_K, pc_bar, omega, M_gmol, T_K, kij=None, ref_comp=0,
-                 kappa_ref=0.02, tau=1.0, a_ref=0.0, b_ref=0.0, R_lu=0.0):
+                 kappa_ref=0.02, tau=1.0, a_ref=0.0, b_ref=0.0, R_lu=0.0, eos="PR"):
         self._arrs = [np.ascontiguousarray(np.asarray(v, dtype=np.float64))
                       for v in (Tc_K, pc_bar, omega, M_gmol)]
         n = len(self._arrs[0])
@@ -146,6 +149,7 @@ class Mixture:
         d.a_ref_lu, d.b_ref_lu, d.R_lu = float(a_ref), float(b_ref), float(R_lu)
         d.kappa_ref_lu = float(kappa_ref)
         d.tau = float(tau)
+        d.eos = EOS_CODES[eos] if isinstance(eos, str) else int(eos)
         h = ctypes.c_void_p()
         check(lib().fuglbm_init_mixture(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h

@@ -35,8 +35,39 @@ fuglbm_status hip_fail(hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
-constexpr double OMEGA_A = 0.457235529;  // PR attraction prefactor (Section II.C)
-constexpr double OMEGA_B = 0.077796074;  // PR co-volume prefactor
+// Cubic equations of state p = RT/(v - b) - a alpha/((v + d1 b)(v + d2 b)):
+// a = omega_a R^2 Tc^2 / pc, b = omega_b R Tc / pc put the critical point at
+// (Tc, pc); u = d1 + d2 and w = d1 d2 are kept exact.
+struct CubicEos {
+    double omega_a, omega_b, d1, d2, u, w;
+};
+
+CubicEos cubic_eos(int eos) {
+    const double s2 = std::sqrt(2.0);
+    const double c2 = std::pow(2.0, 1.0 / 3.0);
+    switch (eos) {
+        case FUGLBM_EOS_SRK:   // Soave-Redlich-Kwong
+            return {1.0 / (9.0 * (c2 - 1.0)), (c2 - 1.0) / 3.0, 1.0, 0.0, 1.0, 0.0};
+        case FUGLBM_EOS_VDW:   // van der Waals
+            return {27.0 / 64.0, 1.0 / 8.0, 0.0, 0.0, 0.0, 0.0};
+        default:               // Peng-Robinson, the paper's (Section II.C)
+            return {0.457235529, 0.077796074, 1.0 + s2, 1.0 - s2, 2.0, -1.0};
+    }
+}
+
+// alpha_i(T): PR as in Section II.C (two branches split at omega = 0.49);
+// SRK with Soave's m(omega); 1 for vdW.
+double cubic_alpha(int eos, double w, double Tr) {
+    if (eos == FUGLBM_EOS_VDW) return 1.0;
+    double m;
+    if (eos == FUGLBM_EOS_SRK)
+        m = 0.480 + 1.574 * w - 0.176 * w * w;
+    else
+        m = w <= 0.49 ? 0.374640 + 1.54226 * w - 0.26992 * w * w
+                      : 0.379642 + 1.48503 * w - 0.164423 * w * w + 0.016666 * w * w * w;
+    const double sa = 1.0 + m * (1.0 - std::sqrt(Tr));
+    return sa * sa;
+}
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -83,6 +114,7 @@ int auto_rows(int nx, int ny, int ncomp, bool fp32) {
 
 struct fuglbm_mixture {
     int N;
+    int eos;
     double RT;
     double b[FUG_MAXC], aa[FUG_MAXC], sqk[FUG_MAXC], M[FUG_MAXC];
     double aij[FUG_MAXC * FUG_MAXC];
@@ -378,6 +410,7 @@ fuglbm_status fuglbm_init_mixture(const fuglbm_mixture_desc *d, fuglbm_mixture *
     if (!d->Tc_K || !d->pc_bar || !d->omega || !d->M_gmol)
         return fail(FUGLBM_EINVAL, "null component array");
     if (d->ref_comp < 0 || d->ref_comp >= N) return fail(FUGLBM_EINVAL, "ref_comp out of range");
+    if (d->eos < FUGLBM_EOS_PR || d->eos > FUGLBM_EOS_VDW) return fail(FUGLBM_EINVAL, "unknown eos");
     if (!(d->T_K > 0) || !std::isfinite(d->T_K)) return fail(FUGLBM_EINVAL, "T_K must be > 0");
     if (!(d->tau > 0.5) || !std::isfinite(d->tau)) return fail(FUGLBM_EINVAL, "tau must be > 1/2");
     if (!(d->kappa_ref_lu >= 0) || !std::isfinite(d->kappa_ref_lu))
@@ -404,24 +437,22 @@ fuglbm_status fuglbm_init_mixture(const fuglbm_mixture_desc *d, fuglbm_mixture *
     const double b_ref = d->b_ref_lu > 0 ? d->b_ref_lu : 2.0 / 21.0;
     const double R = d->R_lu > 0 ? d->R_lu : 1.0;
     const int c = d->ref_comp;
+    const CubicEos E = cubic_eos(d->eos);
     // reference component's critical point in lattice units from a and b
-    const double Tc_ref = (a_ref / b_ref) * (OMEGA_B / OMEGA_A) / R;
-    const double pc_ref = OMEGA_B * R * Tc_ref / b_ref;
+    const double Tc_ref = (a_ref / b_ref) * (E.omega_b / E.omega_a) / R;
+    const double pc_ref = E.omega_b * R * Tc_ref / b_ref;
     const double Tsc = Tc_ref / d->Tc_K[c];     // lattice units per K
     const double psc = pc_ref / d->pc_bar[c];   // lattice units per bar
     m->N = N;
+    m->eos = d->eos;
     m->tau = d->tau;
     m->RT = R * d->T_K * Tsc;
     double a_lu[FUG_MAXC];
     for (int i = 0; i < N; ++i) {
         const double Tc = d->Tc_K[i] * Tsc, pc = d->pc_bar[i] * psc;
-        a_lu[i] = OMEGA_A * R * R * Tc * Tc / pc;
-        m->b[i] = OMEGA_B * R * Tc / pc;
-        const double w = d->omega[i];
-        const double mw = w <= 0.49 ? 0.374640 + 1.54226 * w - 0.26992 * w * w
-                                    : 0.379642 + 1.48503 * w - 0.164423 * w * w + 0.016666 * w * w * w;
-        const double sa = 1.0 + mw * (1.0 - std::sqrt(d->T_K / d->Tc_K[i]));
-        m->aa[i] = a_lu[i] * sa * sa;
+        a_lu[i] = E.omega_a * R * R * Tc * Tc / pc;
+        m->b[i] = E.omega_b * R * Tc / pc;
+        m->aa[i] = a_lu[i] * cubic_alpha(d->eos, d->omega[i], d->T_K / d->Tc_K[i]);
         m->M[i] = d->M_gmol[i] / d->M_gmol[c];
     }
     for (int i = 0; i < N; ++i) {
@@ -539,6 +570,15 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     c.omega = 1.0 / mix->tau;
     c.fcoef = 1.0 - 1.0 / (2.0 * mix->tau);
     c.RT = mix->RT;
+    {
+        const CubicEos E = cubic_eos(mix->eos);
+        c.eos = mix->eos;
+        c.d1 = E.d1;
+        c.d2 = E.d2;
+        c.eu = E.u;
+        c.ew = E.w;
+        c.dk = mix->eos == FUGLBM_EOS_VDW ? 0.0 : 1.0 / (E.d1 - E.d2);
+    }
     for (int i = 0; i < N; ++i) {
         c.b[i] = mix->b[i];
         c.M[i] = mix->M[i];

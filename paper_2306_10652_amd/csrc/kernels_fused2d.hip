@@ -192,9 +192,11 @@ struct Fused {
         }
         double Gx = 0.0, Gy = 0.0;
         if (do_out) grad3(rhm3, rhm2, rhm1, Gx, Gy);
-        // Eq. (9)-(12) in combined-log form for row r-1,
+        // Eq. (9)-(12) in combined-log form for row r-1 (any of the cubics,
+        // p = RT/(v - b) - a/((v + d1 b)(v + d2 b))),
         //   RT ln f_i = RT ln(rt_i c1) + b_i (c2a + lambda c2b) - lambda c3b Sraw_i,
-        // split over two helper waves: A (reciprocals, Z - 1) and B (lambda).
+        // split over two helper waves: A (reciprocals, Z - 1) and B (lambda =
+        // ln[(1 + d1 eta)/(1 + d2 eta)] / (d1 - d2), or eta for vdW).
         if (do_eos && comp == helper_wave<NC>(0)) {
             const int ms = (r - 1) & 1;
             const double rt1 = L.mx[ms][0][lane];
@@ -208,18 +210,18 @@ struct Fused {
             if (!(ome > 0.0)) bad |= FUG_ST_COVOLUME;
             const double inv_ome = frcp(ome);
             const double inv_bm = rt1 * frcp(et1);
-            const double den = 1.0 + 2.0 * et1 - et1 * et1;
+            const double den = 1.0 + C->eu * et1 + C->ew * et1 * et1;
             const double zm1 = et1 * inv_ome - am * rt1 * invRT * frcp(den);
-            const double k = 0.35355339059327373;   // 1 / (2 sqrt 2)
             L.eos[0][lane] = RT * inv_ome;
             L.eos[1][lane] = RT * zm1 * inv_bm;
-            L.eos[2][lane] = k * am * inv_bm * inv_bm;
-            L.eos[3][lane] = 2.0 * k * inv_bm * inv_rt;
+            L.eos[2][lane] = am * inv_bm * inv_bm;
+            L.eos[3][lane] = 2.0 * inv_bm * inv_rt;
         }
         if (do_eos && comp == helper_wave<NC>(1)) {
             const double et1 = L.mx[(r - 1) & 1][1][lane];
-            const double s2 = 1.4142135623730951;
-            L.eos[4][lane] = log((1.0 + (1.0 + s2) * et1) * frcp(1.0 + (1.0 - s2) * et1));
+            L.eos[4][lane] = C->eos == 2
+                                 ? et1
+                                 : log((1.0 + C->d1 * et1) * frcp(1.0 + C->d2 * et1)) * C->dk;
         }
         __syncthreads();
         // ---- phase 2: s(r); psi_i(r-1); F_i(y); Sraw_i(r); helper sums of row r

@@ -124,12 +124,12 @@ __global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict_
         }
     }
     const double RT = c->RT;
-    const MixSums m = pr_mixture(rtt, eta, am, RT);
+    const MixSums m = cubic_mixture(c, rtt, eta, am, RT);
     bad |= m.bad;
 #pragma unroll
     for (int i = 0; i < FUG_MAXC; ++i) {
         if (i < N) {
-            const double v = pr_RTlnf(m, RT, rt[i], c->b[i], S[i]);
+            const double v = cubic_RTlnf(m, RT, rt[i], c->b[i], S[i]);
             if (!isfinite(v)) bad |= FUG_ST_NONFINITE;
             psi_f[(int64_t)i * ns + s] = v;
         }

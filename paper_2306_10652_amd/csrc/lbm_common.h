@@ -1,6 +1,7 @@
 // Device-side definitions shared by the gfx950 kernels and the host library:
 // per-simulation constant block, lattice velocity sets, the local
-// Peng-Robinson fugacity and the per-(component, direction) collision.
+// cubic-EOS (Peng-Robinson, SRK, vdW) fugacity and the per-(component,
+// direction) collision.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,11 +20,14 @@ struct SimConst {
     int32_t N;            // components
     int32_t lattice;      // 0 D2Q9, 1 D3Q19
     int32_t nx, ny, nz;
-    int32_t pad0;
+    int32_t eos;          // 0 Peng-Robinson, 1 SRK, 2 van der Waals
     int64_t nsites;
     double omega;         // 1 / tau
     double fcoef;         // 1 - 1 / (2 tau)
     double RT;
+    // cubic p = RT/(v - b) - a alpha/((v + d1 b)(v + d2 b)):  d1, d2,
+    // u = d1 + d2, w = d1 d2 (exact per EOS) and dk = 1/(d1 - d2) (0 for vdW)
+    double d1, d2, eu, ew, dk;
     double b[FUG_MAXC];
     double M[FUG_MAXC];
     double invM[FUG_MAXC];
@@ -74,26 +78,34 @@ struct D3Q19 {
 };
 
 // ---------------------------------------------------------------------------
-// Peng-Robinson ln f_i for one component, given mixture sums at a site.
+// Cubic-EOS ln f_i for one component, given mixture sums at a site.
 //   eta = b_m rt = sum_j b_j rt_j,  am = sum_ij x_i x_j (a alpha)_ij,
 //   Si  = sum_j x_j (a alpha)_ij.
 // Returns RT ln f_i in the combined-logarithm form (defined for p <= 0):
-//   RT ln(rt_i RT/(1-eta)) + RT (b_i/b_m)(Z-1)
-//     - Lambda/(2 sqrt2 b_m) (2 S_i - a_m b_i / b_m),
-//   Lambda = ln[(1 + (1+sqrt2) eta) / (1 + (1-sqrt2) eta)].
+//   RT ln(rt_i RT/(1-eta)) + RT (b_i/b_m)(Z-1) - (Lhat/b_m) (2 S_i - a_m b_i / b_m),
+//   Lhat = ln[(1 + d1 eta) / (1 + d2 eta)] / (d1 - d2)   (PR: Eq. (12); SRK),
+//   Lhat = eta                                           (vdW, the d1 = d2 -> 0 limit),
+//   Z - 1 = eta/(1 - eta) - am rt / (RT (1 + u eta + w eta^2)).
 // The terms shared by all components are passed in precomputed.
 // ---------------------------------------------------------------------------
 struct MixSums {
     double rt;         // total molar density
     double inv_bm;     // 1 / b_m
     double zm1;        // Z - 1
-    double lam_c;      // Lambda / (2 sqrt2 b_m)
+    double lam_c;      // Lhat / b_m
     double am;
     double log_pref;   // ln(RT / (1 - eta))
     uint32_t bad;      // status bits
 };
 
-__device__ __forceinline__ MixSums pr_mixture(double rt, double eta, double am, double RT) {
+// Lhat of the EOS (uniform branch on the EOS kind).
+__device__ __forceinline__ double eos_lhat(const SimConst *c, double eta) {
+    if (c->eos == 2) return eta;
+    return log((1.0 + c->d1 * eta) / (1.0 + c->d2 * eta)) * c->dk;
+}
+
+__device__ __forceinline__ MixSums cubic_mixture(const SimConst *c, double rt, double eta,
+                                                 double am, double RT) {
     MixSums m;
     m.rt = rt;
     m.am = am;
@@ -101,18 +113,16 @@ __device__ __forceinline__ MixSums pr_mixture(double rt, double eta, double am, 
     m.bad = (one_m_eta > 0.0) ? 0u : FUG_ST_COVOLUME;
     const double bm = eta / rt;
     m.inv_bm = 1.0 / bm;
-    const double den = 1.0 + 2.0 * eta - eta * eta;
+    const double den = 1.0 + c->eu * eta + c->ew * eta * eta;
     // Z - 1 = p / (rt RT) - 1,  p = rt RT/(1 - eta) - am rt^2 / den
     m.zm1 = eta / one_m_eta - am * rt / (RT * den);
-    const double s2 = 1.4142135623730951;
-    const double lam = log((1.0 + (1.0 + s2) * eta) / (1.0 + (1.0 - s2) * eta));
-    m.lam_c = lam * m.inv_bm * (0.5 / s2);
+    m.lam_c = eos_lhat(c, eta) * m.inv_bm;
     m.log_pref = log(RT / one_m_eta);
     return m;
 }
 
-__device__ __forceinline__ double pr_RTlnf(const MixSums &m, double RT, double rt_i,
-                                           double b_i, double S_i) {
+__device__ __forceinline__ double cubic_RTlnf(const MixSums &m, double RT, double rt_i,
+                                              double b_i, double S_i) {
     const double bi_bm = b_i * m.inv_bm;
     return RT * (log(rt_i) + m.log_pref + bi_bm * m.zm1)
          - m.lam_c * (2.0 * S_i - m.am * bi_bm);

@@ -41,15 +41,17 @@ def test_header_and_library_export_the_same_functions():
     (C.N_ALKANES, 325.0, 4),
     ([C.TABLE_I["C1"]], 177.24, None),
 ])
-def test_lattice_constants_match_oracle_units(comps, T, kij_seed):
+@pytest.mark.parametrize("eos", ["PR", "SRK", "vdW"])
+def test_lattice_constants_match_oracle_units(comps, T, kij_seed, eos):
     """The library's own unit conversion (Section III.A anchors, Eq. (6)-(8)
-    kappa, alpha(T)) reproduces the oracle's, independently written."""
+    kappa, alpha(T)) reproduces the oracle's, independently written, for
+    each cubic."""
     capi = _capi()
     from inputs.fields import draw_kij
     from oracle.lbm import oracle_mixture
     kij = None if kij_seed is None else draw_kij(len(comps), 0.0, 0.05, kij_seed)
-    mix = capi.Mixture.from_components(comps, T, kij, kappa_ref=0.03, tau=0.8)
-    om = oracle_mixture(comps, T, kij, kappa_ref=0.03, tau=0.8)
+    mix = capi.Mixture.from_components(comps, T, kij, kappa_ref=0.03, tau=0.8, eos=eos)
+    om = oracle_mixture(comps, T, kij, kappa_ref=0.03, tau=0.8, eos=eos)
     np.testing.assert_allclose(mix.lattice_constants(), om.lattice_constants(), rtol=1e-13,
                                atol=0)
 
@@ -82,6 +84,9 @@ def test_mixture_argument_validation():
         capi.Mixture.from_components(c, -1.0)
     with pytest.raises(capi.FuglbmError):
         capi.Mixture([1.0] * 17, [1.0] * 17, [0.0] * 17, [1.0] * 17, 300.0)
+    with pytest.raises(capi.FuglbmError) as e:
+        capi.Mixture.from_components(c, 250.0, eos=3)
+    assert e.value.status == 1
 
 
 def test_fields_bytes():

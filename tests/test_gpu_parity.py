@@ -83,6 +83,25 @@ def test_ragged_grids_few_steps(shape, N, rows):
         assert err <= 1e-12 and e <= 1e-12
 
 
+@pytest.mark.parametrize("eos", ["SRK", "vdW"])
+@pytest.mark.parametrize("lattice,shape,N,steps,seed", [(0, (67, 45), 3, 300, 1),
+                                                        (0, (125, 17), 7, 100, 342),
+                                                        (1, (20, 18, 16), 3, 60, 113)])
+def test_other_cubics_fp64(eos, lattice, shape, N, steps, seed):
+    """The SRK and vdW equations of state: the fused D2Q9 kernel and the
+    D3Q19 path against the oracle with the same cubic, FP64, <= 1e-10.
+    (Seeds are draws the oracle itself advances without leaving the EOS
+    domain; a quenched random droplet can, for either side alike.)"""
+    wl = W.random_droplet(N, shape, seed=seed, lattice=lattice, eos=eos)
+    o = wl.oracle()
+    assert o.run(steps) == 0
+    g = run_gpu(wl, steps)
+    e = rel_err(g["rho"], o.rho())
+    report("cubic", eos=eos, lattice=lattice, shape=shape, N=N, rho_rel=e)
+    assert g["status"] == 0
+    assert e <= 1e-10
+
+
 @pytest.mark.parametrize("case", [1, 2, 3, 4, 5, 6])
 def test_vle_cases_fp64(case):
     """256 x 32 flat-interface slabs of Table II cases 1-6, 500 steps."""

@@ -1,7 +1,8 @@
 """Physics checks of the GPU path at equilibrium, against the oracle's
 thermodynamics (what the paper validates in Section III):
 
-* pure C1 flat interface -> Maxwell coexistence densities (Table II case 1);
+* pure C1 flat interface -> Maxwell coexistence densities (Table II case 1),
+  with the paper's PR and with SRK / vdW in its place;
 * binary C1/C2 flat interface -> the flash tie line at the LBM's own
   pressure (two components at fixed T have one degree of freedom, so the
   bulk phases must sit on the flash at the measured p);
@@ -45,21 +46,25 @@ def run_to_equilibrium(mix, shape, rho, tol, max_steps, chunk=2000, precision=0,
     return out
 
 
-def test_flat_interface_reaches_maxwell():
+@pytest.mark.parametrize("eos", ["PR", "SRK", "vdW"])
+def test_flat_interface_reaches_maxwell(eos):
+    """Pure C1 at 177.24 K (Table II case 1) on a 256 x 4 slab relaxes to the
+    Maxwell coexistence densities of its EOS: the paper's PR, and SRK and
+    vdW in its place (only ln f_i and p change)."""
     from oracle import thermo as th
     from oracle.lbm import oracle_mixture
     c1 = C.TABLE_I["C1"]
-    om = oracle_mixture([c1], 177.24)
+    om = oracle_mixture([c1], 177.24, eos=eos)
     ps, rV, rL = th.maxwell(om.pr)
     capi = _capi()
-    mix = capi.Mixture.from_components([c1], 177.24)
+    mix = capi.Mixture.from_components([c1], 177.24, eos=eos)
     n = 256
     rho = Fi.slab(n, 4, [om.M[0] * rV * 0.98], [om.M[0] * rL * 1.02], 0.5)
     out = run_to_equilibrium(mix, (n, 4), rho, 1e-13, 200000)
     rt = out["rho"][0, 0, 0] / om.M[0]
     eV = rt[0:8].mean() / rV - 1
     eL = rt[n // 2 - 4:n // 2 + 4].mean() / rL - 1
-    report("maxwell", steps=out["steps"], residual=out["residual"], errV=eV, errL=eL,
+    report("maxwell", eos=eos, steps=out["steps"], residual=out["residual"], errV=eV, errL=eL,
            umax=float(np.abs(out["u"]).max()))
     assert abs(eV) < 1e-5 and abs(eL) < 1e-5
     assert np.abs(out["u"]).max() < 1e-12

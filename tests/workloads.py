@@ -17,9 +17,11 @@ def states():
 
 
 class Workload:
-    def __init__(self, comps, T, rho, shape, kij=None, kappa_ref=0.02, tau=1.0, lattice=0):
+    def __init__(self, comps, T, rho, shape, kij=None, kappa_ref=0.02, tau=1.0, lattice=0,
+                 eos="PR"):
         self.comps, self.T, self.rho, self.shape = list(comps), T, rho, tuple(shape)
         self.kij, self.kappa_ref, self.tau, self.lattice = kij, kappa_ref, tau, lattice
+        self.eos = eos
 
     @property
     def N(self):
@@ -28,11 +30,12 @@ class Workload:
     def gpu_mixture(self):
         from paper_2306_10652_amd.capi import Mixture
         return Mixture.from_components(self.comps, self.T, self.kij,
-                                       kappa_ref=self.kappa_ref, tau=self.tau)
+                                       kappa_ref=self.kappa_ref, tau=self.tau, eos=self.eos)
 
     def oracle(self):
         from oracle.lbm import OracleLBM, oracle_mixture
-        m = oracle_mixture(self.comps, self.T, self.kij, kappa_ref=self.kappa_ref, tau=self.tau)
+        m = oracle_mixture(self.comps, self.T, self.kij, kappa_ref=self.kappa_ref, tau=self.tau,
+                           eos=self.eos)
         return OracleLBM(m, self.lattice, self.shape, self.rho)
 
 
@@ -60,9 +63,10 @@ def spinodal10(n=1024, noise=1e-2, seed=4):
     return Workload(C.N_ALKANES, 325.0, rho, (n, n), kij=np.array(st["kij"]))
 
 
-def random_droplet(N, shape, seed, lattice=0, noise=1e-2):
+def random_droplet(N, shape, seed, lattice=0, noise=1e-2, eos="PR"):
     """Small ragged-grid droplet/sphere of the first N n-alkanes (N <= 10) or
-    of C1 pseudo-components (N > 10); used for edge-case parity."""
+    of C1 pseudo-components (N > 10); used for edge-case parity.  ``eos``
+    picks the cubic (PR, SRK, vdW)."""
     rng = np.random.default_rng(seed)
     if N <= 10:
         comps = C.N_ALKANES[:N]
@@ -72,7 +76,7 @@ def random_droplet(N, shape, seed, lattice=0, noise=1e-2):
     nz = shape[2] if len(shape) > 2 else 1
     # liquid-like and vapour-like molar densities at eta = 0.55 / 0.05
     from oracle.lbm import oracle_mixture   # constants only (b_i), test side
-    m = oracle_mixture(comps, 300.0)
+    m = oracle_mixture(comps, 300.0, eos=eos)
     x = rng.dirichlet(np.ones(N))
     rtL = x * 0.55 / (x @ m.pr.b)
     rtV = x * 0.05 / (x @ m.pr.b)
@@ -83,4 +87,5 @@ def random_droplet(N, shape, seed, lattice=0, noise=1e-2):
     t = np.tanh(2 * (r - R) / 4.0)
     rho = (0.5 * (rho_L + rho_V))[:, None, None, None] - (0.5 * (rho_L - rho_V))[:, None, None, None] * t
     rho = Fi.add_noise(rho, noise, seed)
-    return Workload(comps, 300.0, rho, (nx, ny, nz) if lattice else (nx, ny), lattice=lattice)
+    return Workload(comps, 300.0, rho, (nx, ny, nz) if lattice else (nx, ny), lattice=lattice,
+                    eos=eos)
