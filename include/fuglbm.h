@@ -175,20 +175,23 @@ fuglbm_status fuglbm_read_populations(fuglbm_sim *sim, double *g_out);
 fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int64_t step);
 
 /* Launch tuning: kernel 0 = automatic, 1 = three-pass generic kernels,
- * 2 = fused one-pass D2Q9 kernel; rows = output rows per fused work item
- * (>= 1, fixed), or 0 = autotuned: the next fuglbm_step_n times a few
- * trial launches per candidate (they read the current state and write the
- * spare buffer, so the state does not move) and keeps the fastest; the
- * choice is cached per (nx, ny, ncomp, precision) for the process.  The
- * state does not depend on rows.  fuglbm_step_many tunes one rows value
+ * 2 = fused one-pass D2Q9 kernel (register ring), 3 = fused one-pass D2Q9
+ * kernel with store wavefronts (ncomp <= 10; bit-identical results);
+ * rows = output rows per fused work item (>= 1, fixed), or 0 = autotuned:
+ * the next fuglbm_step_n times a few trial launches per candidate (they
+ * read the current state and write the spare buffer, so the state does
+ * not move) and keeps the fastest; with kernel 0 both fused variants are
+ * timed and the faster (variant, rows) is kept.  The choice is cached per
+ * (nx, ny, ncomp, precision) for the process.  The state does not depend
+ * on the variant or on rows.  fuglbm_step_many tunes one (variant, rows)
  * per batch shape the same way unless a member has fixed rows.
  * Autotuning is the default.  EINVAL for a kernel the simulation cannot
  * use, or rows < 0. */
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *sim, int32_t kernel, int32_t rows);
 
-/* Query the launch tuning in use: kernel (1 generic, 2 fused) and fused
- * rows per work item (0 for the generic kernels; with autotuning, the
- * value chosen once a step has run). */
+/* Query the launch tuning in use: kernel (1 generic, 2 or 3 fused) and
+ * fused rows per work item (0 for the generic kernels; with autotuning,
+ * the values chosen once a step has run). */
 fuglbm_status fuglbm_get_tuning(const fuglbm_sim *sim, int32_t *kernel, int32_t *rows);
 
 /* Query: Q, spatial dimension, sites, bytes moved per step by the

@@ -92,9 +92,29 @@ int compute_units() {
     return cus;
 }
 
-int auto_rows(int nx, int ny, int ncomp, bool fp32) {
+// Fused variants: 2 = register-ring kernel, 3 = store-wave kernel.
+bool ws_usable(int ncomp, bool fp32) {
+    return ncomp <= fused_ws_max_comp() && fused_ws_fits(ncomp, fp32) &&
+           fused_ws_blocks_per_cu(ncomp, fp32) > 0;
+}
+
+int blocks_per_cu(int kernel, int ncomp, bool fp32) {
+    return kernel == 3 ? fused_ws_blocks_per_cu(ncomp, fp32) : fused_blocks_per_cu(ncomp, fp32);
+}
+
+hipError_t launch_fused(int kernel, int ncomp, bool fp32, const FusedItem *items, int nitems,
+                        const FusedSim *sims, int flip, hipStream_t st) {
+    return kernel == 3 ? launch_fused_d2q9_ws(ncomp, fp32, items, nitems, sims, flip, st)
+                       : launch_fused_d2q9(ncomp, fp32, items, nitems, sims, flip, st);
+}
+
+// The fused variant used before (or without) timing: the store-wave kernel
+// where it is built and fits, else the register-ring kernel.
+int default_fused(int ncomp, bool fp32) { return ws_usable(ncomp, fp32) ? 3 : 2; }
+
+int auto_rows(int nx, int ny, int ncomp, bool fp32, int kernel = 2) {
     const int strips = (nx + FUSED_OUT - 1) / FUSED_OUT;
-    const int64_t slots = (int64_t)compute_units() * fused_blocks_per_cu(ncomp, fp32);
+    const int64_t slots = (int64_t)compute_units() * blocks_per_cu(kernel, ncomp, fp32);
     if (ny <= 8) return ny;
     int best = 8;
     int64_t best_cost = INT64_MAX;
@@ -181,8 +201,9 @@ struct fuglbm_sim {
     FusedSim *fsim;
     FusedItem *items;
     int nitems;
-    int kernel;            // 1 generic, 2 fused
+    int kernel;            // 1 generic, 2 fused (register ring), 3 fused (store waves)
     int rows;
+    bool auto_kernel;      // fused variant chosen by timing (not fixed by the caller)
     bool autotune;         // rows chosen by timing (not fixed by the caller)
     bool tuned;            // autotune done (or answered from the cache)
     int64_t step;
@@ -254,8 +275,9 @@ void drop_graph(fuglbm_sim *s) {
 }
 
 hipError_t launch_one_step(fuglbm_sim *s, int flip_parity, hipStream_t st) {
-    if (s->kernel == 2)
-        return launch_fused_d2q9(s->N, s->fp32, s->items, s->nitems, s->fsim, flip_parity, st);
+    if (s->kernel >= 2)
+        return launch_fused(s->kernel, s->N, s->fp32, s->items, s->nitems, s->fsim, flip_parity,
+                            st);
     return launch_step_generic(s->lattice, s->fp32, s->dc, s->N, s->nx, s->ny, s->nz, s->buf[flip_parity],
                                s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
                                s->u_f, s->status, st);
@@ -330,7 +352,7 @@ struct Timer {
 // for every candidate r; returns the fastest.
 template <class Prep, class Launch>
 fuglbm_status time_candidates(const std::vector<int> &cand, hipStream_t st, Prep prepare,
-                              Launch launch, int &best) {
+                              Launch launch, int &best, float *best_time = nullptr) {
     Timer tm;
     if (!tm.ok()) return fail(FUGLBM_EDEVICE, "hipEventCreate");
     float best_ms = 1e30f;
@@ -354,6 +376,7 @@ fuglbm_status time_candidates(const std::vector<int> &cand, hipStream_t st, Prep
             best = cand[k];
         }
     }
+    if (best_time) *best_time = best_ms;
     return FUGLBM_OK;
 }
 
@@ -369,21 +392,43 @@ fuglbm_status set_rows(fuglbm_sim *s, int rows, hipStream_t st) {
     return build_items(s);
 }
 
+// With the variant left to the tuner, both fused variants are timed (each
+// at its own rows candidates) and the faster (variant, rows) is kept; the
+// cache entry holds kernel * 65536 + rows.
 fuglbm_status autotune_rows(fuglbm_sim *s, hipStream_t st) {
-    const auto key = std::make_tuple(s->nx, s->ny, s->N, s->fp32 ? 1 : 0);
+    const bool both = s->auto_kernel && ws_usable(s->N, s->fp32);
+    const int tag = both ? 0 : s->kernel;
+    const auto key = std::make_tuple(s->nx, s->ny, s->N, (s->fp32 ? 1 : 0) + 2 * tag);
     auto hit = tune_cache().find(key);
-    int best = 0;
+    int best_k = s->kernel, best = 0;
     if (hit != tune_cache().end()) {
-        best = hit->second;
+        best_k = hit->second >> 16;
+        best = hit->second & 0xffff;
     } else {
-        const std::vector<int> cand =
-            tune_candidates(s->ny, auto_rows(s->nx, s->ny, s->N, s->fp32));
-        fuglbm_status rc = time_candidates(
-            cand, st, [&](int r) { return set_rows(s, r, st); },
-            [&]() { return launch_one_step(s, s->parity, st); }, best);
-        if (rc != FUGLBM_OK) return rc;
-        tune_cache()[key] = best;
+        float best_ms = 1e30f;
+        for (int k : {2, 3}) {
+            if (both ? false : k != s->kernel) continue;
+            if (k == 3 && !ws_usable(s->N, s->fp32)) continue;
+            HIP_TRY(hipStreamSynchronize(st));
+            s->kernel = k;
+            const std::vector<int> cand =
+                tune_candidates(s->ny, auto_rows(s->nx, s->ny, s->N, s->fp32, k));
+            int r = 0;
+            float ms = 0.f;
+            fuglbm_status rc = time_candidates(
+                cand, st, [&](int rr) { return set_rows(s, rr, st); },
+                [&]() { return launch_one_step(s, s->parity, st); }, r, &ms);
+            if (rc != FUGLBM_OK) return rc;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_k = k;
+                best = r;
+            }
+        }
+        tune_cache()[key] = best_k * 65536 + best;
     }
+    HIP_TRY(hipStreamSynchronize(st));
+    s->kernel = best_k;
     s->tuned = true;
     return set_rows(s, best, st);
 }
@@ -613,8 +658,9 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     e = hipMemcpy(s->fsim, &fs, sizeof(FusedSim), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(e, "upload fused sim"));
     const bool fused = fused_fits(s);
-    s->kernel = fused ? 2 : 1;
-    s->rows = fused ? auto_rows(nx, ny, N, s->fp32) : 0;
+    s->kernel = fused ? default_fused(N, s->fp32) : 1;
+    s->rows = fused ? auto_rows(nx, ny, N, s->fp32, s->kernel) : 0;
+    s->auto_kernel = fused;
     if (fused) {
         rc = build_items(s);
         if (rc != FUGLBM_OK) return bail(rc);
@@ -633,20 +679,23 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
 fuglbm_status fuglbm_get_tuning(const fuglbm_sim *s, int32_t *kernel, int32_t *rows) {
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
     if (kernel) *kernel = s->kernel;
-    if (rows) *rows = s->kernel == 2 ? s->rows : 0;
+    if (rows) *rows = s->kernel >= 2 ? s->rows : 0;
     return FUGLBM_OK;
 }
 
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
-    if (kernel < 0 || kernel > 2) return fail(FUGLBM_EINVAL, "kernel must be 0, 1 or 2");
-    if (kernel == 2 && !fused_fits(s))
+    if (kernel < 0 || kernel > 3) return fail(FUGLBM_EINVAL, "kernel must be 0, 1, 2 or 3");
+    if (kernel >= 2 && !fused_fits(s))
         return fail(FUGLBM_EINVAL, "the fused kernel is D2Q9 only, with < 2^32 elements per buffer");
+    if (kernel == 3 && !ws_usable(s->N, s->fp32))
+        return fail(FUGLBM_EINVAL, "the store-wave fused kernel is built for at most 10 components");
     if (rows < 0) return fail(FUGLBM_EINVAL, "rows must be >= 0");
-    const int k = kernel == 0 ? (fused_fits(s) ? 2 : 1) : kernel;
+    const int k = kernel == 0 ? (fused_fits(s) ? default_fused(s->N, s->fp32) : 1) : kernel;
+    s->auto_kernel = kernel == 0 && k >= 2;
     int r = s->rows;
-    if (k == 2) {
-        r = rows == 0 ? auto_rows(s->nx, s->ny, s->N, s->fp32) : std::min<int>(rows, s->ny);
+    if (k >= 2) {
+        r = rows == 0 ? auto_rows(s->nx, s->ny, s->N, s->fp32, k) : std::min<int>(rows, s->ny);
         s->autotune = rows == 0;
         s->tuned = false;
     }
@@ -680,7 +729,7 @@ fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
     hipStream_t st = (hipStream_t)hip_stream;
     s->last_stream = st;
     int64_t left = nsteps;
-    if (left > 0 && s->kernel == 2 && s->autotune && !s->tuned) {
+    if (left > 0 && s->kernel >= 2 && s->autotune && !s->tuned) {
         fuglbm_status rc = autotune_rows(s, st);
         if (rc != FUGLBM_OK) return rc;
     }
@@ -883,6 +932,7 @@ struct BatchTable {
     FusedItem *ditems = nullptr;
     size_t cap_sims = 0, cap_items = 0;
     int nitems = 0;
+    int kernel = 2;                   // fused variant of the launches
     hipGraphExec_t graph = nullptr;   // GRAPH_STEPS launches starting at flip 0
     hipStream_t last_stream = nullptr;
     bool used = false;                // last_stream is meaningful
@@ -894,7 +944,8 @@ fuglbm_status batch_graph(BatchTable &bt, int ncomp, bool fp32) {
     if (!cs) return fail(FUGLBM_EDEVICE, "cannot create capture stream");
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < GRAPH_STEPS; ++k) {
-        hipError_t e = launch_fused_d2q9(ncomp, fp32, bt.ditems, bt.nitems, bt.dsims, k & 1, cs);
+        hipError_t e =
+            launch_fused(bt.kernel, ncomp, fp32, bt.ditems, bt.nitems, bt.dsims, k & 1, cs);
         if (e != hipSuccess) {
             hipGraph_t g;
             hipStreamEndCapture(cs, &g);
@@ -918,13 +969,15 @@ std::map<std::pair<int, int>, BatchTable> &batch_tables() {
 }
 
 // rows > 0: every member uses min(rows, ny) rows per item; 0: its own.
+// kernel: the fused variant (0: that of the first member).
 fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, hipStream_t st,
-                          int rows = 0) {
+                          int rows = 0, int kernel = 0) {
     HIP_TRY(hipStreamSynchronize(st));  // the old table may still be read by queued launches
     if (bt.graph) {
         hipGraphExecDestroy(bt.graph);
         bt.graph = nullptr;
     }
+    bt.kernel = kernel ? kernel : group[0]->kernel;
     std::vector<FusedSim> hs;
     std::vector<FusedItem> logical;
     for (size_t k = 0; k < group.size(); ++k) {
@@ -989,26 +1042,44 @@ static int log2_class(int64_t v) {
 
 fuglbm_status tune_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group, int nc, bool f32,
                          hipStream_t st) {
-    static std::map<std::tuple<int, int, int, int>, int> cache;
+    static std::map<std::tuple<int, int, int, int>, int> cache;   // kernel * 65536 + rows
     for (auto *s : group)
         if (!s->autotune) return build_batch(bt, group, st);   // rows fixed by the caller
+    bool auto_k = true;
+    for (auto *s : group) auto_k = auto_k && s->auto_kernel;
+    const bool both = auto_k && ws_usable(nc, f32);
     int64_t strip_rows = 0;
     int ny_max = 1;
     for (auto *s : group) {
         strip_rows += (int64_t)((s->nx + FUSED_OUT - 1) / FUSED_OUT) * s->ny;
         ny_max = std::max(ny_max, s->ny);
     }
-    const auto key = std::make_tuple(nc, f32 ? 1 : 0, log2_class(strip_rows), log2_class(ny_max));
+    const int tag = both ? 0 : group[0]->kernel;
+    const auto key = std::make_tuple(nc, (f32 ? 1 : 0) + 2 * tag, log2_class(strip_rows),
+                                     log2_class(ny_max));
     auto hit = cache.find(key);
-    if (hit != cache.end()) return build_batch(bt, group, st, hit->second);
-    int best = 0;
-    fuglbm_status rc = time_candidates(
-        tune_candidates(ny_max, 0), st, [&](int r) { return build_batch(bt, group, st, r); },
-        [&]() { return launch_fused_d2q9(nc, f32, bt.ditems, bt.nitems, bt.dsims, 0, st); },
-        best);
-    if (rc != FUGLBM_OK) return rc;
-    cache[key] = best;
-    return build_batch(bt, group, st, best);
+    if (hit != cache.end())
+        return build_batch(bt, group, st, hit->second & 0xffff, hit->second >> 16);
+    int best_k = group[0]->kernel, best = 0;
+    float best_ms = 1e30f;
+    for (int k : {2, 3}) {
+        if (both ? false : k != group[0]->kernel) continue;
+        if (k == 3 && !ws_usable(nc, f32)) continue;
+        int r = 0;
+        float ms = 0.f;
+        fuglbm_status rc = time_candidates(
+            tune_candidates(ny_max, 0), st, [&](int rr) { return build_batch(bt, group, st, rr, k); },
+            [&]() { return launch_fused(k, nc, f32, bt.ditems, bt.nitems, bt.dsims, 0, st); }, r,
+            &ms);
+        if (rc != FUGLBM_OK) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_k = k;
+            best = r;
+        }
+    }
+    cache[key] = best_k * 65536 + best;
+    return build_batch(bt, group, st, best, best_k);
 }
 
 }  // namespace
@@ -1050,7 +1121,7 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             skipped = true;
             continue;
         }
-        if (s->lattice == FUGLBM_D2Q9 && s->kernel == 2)
+        if (s->lattice == FUGLBM_D2Q9 && s->kernel >= 2)
             groups[{s->N, s->fp32 ? 1 : 0}].push_back(s);
         else
             others.push_back(s);
@@ -1082,7 +1153,8 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             flip = 0;
         }
         if (left >= 2 * GRAPH_STEPS && flip == 1) {
-            hipError_t e = launch_fused_d2q9(nc, f32, bt.ditems, bt.nitems, bt.dsims, flip, st);
+            hipError_t e =
+                launch_fused(bt.kernel, nc, f32, bt.ditems, bt.nitems, bt.dsims, flip, st);
             if (e != hipSuccess) return hip_fail(e, "batched step launch");
             flip = 0;
             --left;
@@ -1097,7 +1169,8 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             }
         }
         for (; left > 0; --left) {
-            hipError_t e = launch_fused_d2q9(nc, f32, bt.ditems, bt.nitems, bt.dsims, flip, st);
+            hipError_t e =
+                launch_fused(bt.kernel, nc, f32, bt.ditems, bt.nitems, bt.dsims, flip, st);
             if (e != hipSuccess) return hip_fail(e, "batched step launch");
             flip ^= 1;
         }

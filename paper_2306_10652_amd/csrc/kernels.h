@@ -42,3 +42,12 @@ int fused_blocks_per_cu(int ncomp, bool fp32);
 
 hipError_t launch_fused_d2q9(int ncomp, bool fp32, const FusedItem *items, int nitems,
                              const FusedSim *sims, int flip, hipStream_t st);
+
+// Store-wave variant of the fused D2Q9 step (component waves only load;
+// two extra waves per workgroup store; rows requested three ahead).  Same
+// items, same results bit for bit.  Built for ncomp <= fused_ws_max_comp().
+int fused_ws_max_comp();
+bool fused_ws_fits(int ncomp, bool fp32);
+int fused_ws_blocks_per_cu(int ncomp, bool fp32);
+hipError_t launch_fused_d2q9_ws(int ncomp, bool fp32, const FusedItem *items, int nitems,
+                                const FusedSim *sims, int flip, hipStream_t st);

@@ -143,13 +143,14 @@ def test_sticky_error_and_isolation_in_batch():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_state_independent_of_rows_per_item(precision):
-    """The autotuner times rows-per-item candidates on real steps: that is
-    only sound if every choice gives bitwise the same state."""
+    """The autotuner times fused variants and rows-per-item candidates on
+    real steps: that is only sound if every choice gives bitwise the same
+    state."""
     wl = W.random_droplet(4, (130, 75), seed=11)
     fixed = []
-    for rows in (1, 5, 37):
+    for kernel, rows in ((2, 1), (2, 5), (2, 37), (3, 1), (3, 5), (3, 37)):
         sim = make(wl, precision)
-        sim.set_tuning(2, rows)
+        sim.set_tuning(kernel, rows)
         sim.step_n(150)
         fixed.append(sim.read_populations())
     tuned = make(wl, precision)       # autotuned during its first step_n
