@@ -28,12 +28,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "spinodal10_d2q9_1024x1024"
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fused_d2q9_spinodal10_1024_pmc.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2306_10652_amd", "csrc", "kernels_fused2d.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2306_10652_amd", "csrc", f)
+               for f in ("fused_common.h", "kernels_fused2d.hip", "kernels_fused2d_ws.hip")]
+KERNEL_NAMES = {2: "k_fused_d2q9<10,%s>", 3: "k_fused_d2q9_ws<10,%s>"}
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the fused kernels' sources (the profile summary records the
+    hash it was measured with; a changed kernel voids its traffic figure)."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def build_inputs(n):
@@ -44,15 +51,15 @@ def build_inputs(n):
     return C.N_ALKANES, 325.0, np.array(st["kij"]), rho
 
 
-def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0):
+def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0, kernel=0):
     import torch
     from paper_2306_10652_amd import capi
     comps, T, kij, rho = build_inputs(n)
     mix = capi.Mixture.from_components(comps, T, kij, kappa_ref=0.02, tau=1.0)
     stream = torch.cuda.Stream()
     sim = capi.Simulation(mix, capi.D2Q9, precision, (n, n), rho, stream=stream)
-    if rows:
-        sim.set_tuning(2, rows)         # fixed rows: no tuning launches (profiling runs)
+    if rows or kernel:
+        sim.set_tuning(kernel, rows)    # fixed rows: no tuning launches (profiling runs)
     info = sim.info()
     sim.step_n(warmup)                  # the first call autotunes rows (not timed)
     tuning = sim.get_tuning()
@@ -81,7 +88,7 @@ def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0):
     launch_s = kern_ms * 1e-3 / steps
     alg = info["alg_bytes_per_step"]
     res = dict(csu=csu, wall=wall, ms_per_step=wall * 1e3 / steps, launch_ms=launch_s * 1e3,
-               alg_bytes=alg, achieved_gbs=alg / launch_s / 1e9, kernel=info["kernel"],
+               alg_bytes=alg, achieved_gbs=alg / launch_s / 1e9, kernel=tuning["kernel"],
                rows=tuning["rows"],
                status=d["status"], residual=d["residual"], mass=d["mass"].tolist())
     sim.close()
@@ -261,6 +268,9 @@ def main():
     ap.add_argument("--rows", type=int, default=0,
                     help="fix the fused kernel's rows per work item instead of "
                          "autotuning (profiling runs: no tuning launches)")
+    ap.add_argument("--kernel", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="fix the step kernel (0 = autotuned; 2 / 3 = the two fused "
+                         "variants; with --rows and 0, the default fused variant)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times "
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -285,17 +295,18 @@ def main():
         sys.exit(1)
     if args.precision != "both":
         r = time_gpu(0 if args.precision == "fp64" else 1, args.steps, args.warmup, args.n,
-                     rows=args.rows)
+                     rows=args.rows, kernel=args.kernel)
         print(json.dumps(dict(precision=args.precision, **{k: v for k, v in r.items()
                                                              if k != "mass"})), flush=True)
         return
-    r64 = time_gpu(0, args.steps, args.warmup, args.n)
-    r32 = time_gpu(1, args.steps, args.warmup, args.n)
+    r64 = time_gpu(0, args.steps, args.warmup, args.n, rows=args.rows, kernel=args.kernel)
+    r32 = time_gpu(1, args.steps, args.warmup, args.n, rows=args.rows, kernel=args.kernel)
     traffic = pmc_traffic(r64["alg_bytes"])
     roof = dict(bound="hbm", achieved=round(r64["achieved_gbs"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4),
                 traffic=traffic, alg_bytes_per_launch=r64["alg_bytes"],
-                launch_ms=round(r64["launch_ms"], 5), kernel="k_fused_d2q9<10,double>",
+                launch_ms=round(r64["launch_ms"], 5),
+                kernel=KERNEL_NAMES.get(r64["kernel"], "generic") % "double",
                 rows_per_item=r64["rows"])
     out = dict(metric="component-site updates/s & %HBM roofline; p50/p99 time-to-equilibrium",
                value=round(r64["csu"], 1),
@@ -310,7 +321,9 @@ def main():
                                  achieved_gbs=round(r32["achieved_gbs"], 1),
                                  frac=round(r32["achieved_gbs"] / HBM_PEAK_GBS, 4),
                                  alg_bytes_per_launch=r32["alg_bytes"],
-                                 launch_ms=round(r32["launch_ms"], 5), rows_per_item=r32["rows"]),
+                                 launch_ms=round(r32["launch_ms"], 5),
+                                 kernel=KERNEL_NAMES.get(r32["kernel"], "generic") % "float",
+                                 rows_per_item=r32["rows"]),
                status=[r64["status"], r32["status"]])
     legs = set() if args.no_extra else set(args.legs.split(","))
     if "sweep" in legs:
