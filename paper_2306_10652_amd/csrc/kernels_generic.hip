@@ -324,13 +324,16 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
         const double Fu = Fx * ux + Fy * uy + Fz * uz;
         const double Gu = Gx * ux + Gy * uy + Gz * uz;
         // moving populations first; in FP32 storage their rounding error
-        // goes into the rest population, which stays at this site
+        // goes into the rest population, which stays at this site.  At
+        // tau = 1 the collision does not depend on the old populations
+        // (their moments came from the first pass): they are not read.
+        const bool keep_g = omega != 1.0;
         double err = 0.0;
         // directions in a rolled loop: unrolled, the compiler hoists every
         // load and the kernel needs 256 registers (one wavefront per SIMD)
 #pragma unroll 2
         for (int a = 1; a < L::Q; ++a) {
-            const double gv = (double)*(const ST *)(gsb + P.move(row, i, a, T.x));
+            const double gv = keep_g ? (double)*(const ST *)(gsb + P.move(row, i, a, T.x)) : 0.0;
             const double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu,
                                             Gu, omega, fcoef);
             const ST v = (ST)o;
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
             zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
             *(ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)) = v;
         }
-        const double g0 = *(const double *)(gsb + P.rest(row, i, T.x));
+        const double g0 = keep_g ? *(const double *)(gsb + P.rest(row, i, T.x)) : 0.0;
         const double o0 = collide_one<L>(0, g0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
                                          omega, fcoef);
         *(double *)(gdb + P.rest(row, i, T.x)) = sizeof(ST) == 4 ? o0 - err : o0;

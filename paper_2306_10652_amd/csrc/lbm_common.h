@@ -148,7 +148,9 @@ __device__ __forceinline__ double collide_one(int a, double g, double rho, doubl
     const double geq = (a == 0) ? rho + wa * rho * sq : wa * rho * sq;
     const double Fa = wa * (3.0 * (eF - Fu) + 9.0 * eu * eF)
                     + wa * (-Gu + 3.0 * eu * eG + 0.5 * (3.0 * e2 - (double)L::D) * Gu);
-    return g - omega * (g - geq) + fcoef * Fa;
+    // (1 - omega) g + omega geq: at omega = 1 (tau = 1) the old population
+    // drops out exactly, so a caller may pass g = 0 without reading it
+    return fma(1.0 - omega, g, omega * geq) + fcoef * Fa;
 }
 
 // Population storage of one buffer.  The rest populations are FP64 in both

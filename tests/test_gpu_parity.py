@@ -105,6 +105,24 @@ def test_other_cubics_fp64(eos, lattice, shape, N, steps, seed):
     assert e <= 1e-10
 
 
+@pytest.mark.parametrize("tau", [0.8, 1.3])
+@pytest.mark.parametrize("lattice,shape,kernel", [(0, (67, 45), 3), (0, (67, 45), 2),
+                                                  (0, (67, 45), 1), (1, (14, 12, 10), 0)])
+def test_tau_other_than_one(tau, lattice, shape, kernel):
+    """tau != 1 keeps the (1 - 1/tau) g part of the collision (at tau = 1 the
+    generic kernels do not read the old populations): every step kernel
+    against the oracle at the same tau, FP64, 100 steps, <= 1e-10."""
+    wl = W.random_droplet(3, shape, seed=21, lattice=lattice)
+    wl.tau = tau
+    o = wl.oracle()
+    assert o.run(100) == 0
+    g = run_gpu(wl, 100, kernel=kernel)
+    e = rel_err(g["rho"], o.rho())
+    report("tau", tau=tau, lattice=lattice, kernel=kernel, rho_rel=e)
+    assert g["status"] == 0
+    assert e <= 1e-10
+
+
 @pytest.mark.parametrize("case", [1, 2, 3, 4, 5, 6])
 def test_vle_cases_fp64(case):
     """256 x 32 flat-interface slabs of Table II cases 1-6, 500 steps."""
