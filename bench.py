@@ -155,34 +155,37 @@ def sweep_leg(steps=512, acc_steps=200000, acc_count=8):
 
 def time_vs_n_leg(steps=2000):
     """Per-step time against component count: Table II cases 1-6 as
-    256 x 32 flat slabs, FP64 (the paper reports linear growth in N)."""
+    256 x 32 flat slabs, FP64 (the paper reports linear growth in N), and
+    the same with FP32 storage."""
     import torch
     from paper_2306_10652_amd import capi
     from inputs import components as C
     from inputs import fields as Fi
     S = Fi.load_phase_states()
-    Ns, us = [], []
+    Ns, us, us32 = [], [], []
     st = torch.cuda.Stream()
     for case in range(1, 7):
         comps, T, _ = C.table_ii_components(case)
         v = S["vle%d" % case]
         rho = Fi.slab(256, 32, v["rho_V"], v["rho_L"], 0.5)
         mix = capi.Mixture.from_components(comps, T)
-        sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (256, 32), rho, stream=st)
-        sim.step_n(256)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.step_n(steps)
-        torch.cuda.synchronize()
-        us.append((time.perf_counter() - t0) / steps * 1e6)
+        for prec, out in ((capi.FP64, us), (capi.FP32_STORAGE, us32)):
+            sim = capi.Simulation(mix, capi.D2Q9, prec, (256, 32), rho, stream=st)
+            sim.step_n(256)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step_n(steps)
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t0) / steps * 1e6)
+            sim.close()
         Ns.append(len(comps))
-        sim.close()
     A = np.vstack([Ns, np.ones(len(Ns))]).T
     coef, *_ = np.linalg.lstsq(A, np.array(us), rcond=None)
     fit = A @ coef
     r2 = 1 - np.sum((np.array(us) - fit) ** 2) / np.sum((np.array(us) - np.mean(us)) ** 2)
     return dict(grid=[256, 32], N=Ns, us_per_step=[round(u, 2) for u in us],
-                slope_us_per_component=round(coef[0], 3), r2=round(float(r2), 4))
+                slope_us_per_component=round(coef[0], 3), r2=round(float(r2), 4),
+                us_per_step_fp32_storage=[round(u, 2) for u in us32])
 
 
 def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=None):
@@ -220,14 +223,26 @@ def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=No
     return st
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, budget_s=15.0):
-    """The CPU oracle on a bounded sample: whole 1024^2 steps until ~budget."""
-    from oracle.lbm import OracleLBM, oracle_mixture, build_oracle
+    """The CPU oracle on a bounded sample: whole 1024^2 steps until ~budget
+    with every thread OpenMP gets, then one step on one thread."""
+    from oracle.lbm import OracleLBM, oracle_mixture, build_oracle, set_threads
     build_oracle()
     comps, T, kij, rho = build_inputs(n)
     m = oracle_mixture(comps, T, kij, kappa_ref=0.02, tau=1.0)
     o = OracleLBM(m, 0, (n, n), rho)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = set_threads(0)
     t0 = time.perf_counter()
     k = 0
     while True:
@@ -236,9 +251,18 @@ def cpu_baseline(n, budget_s=15.0):
         if time.perf_counter() - t0 > budget_s or k >= 20:
             break
     dt = time.perf_counter() - t0
-    return dict(value=len(comps) * n * n * k / dt, unit="CSU/s", cores=threads, kind="oracle",
+    set_threads(1)
+    t1 = time.perf_counter()
+    o.run(1)
+    dt1 = time.perf_counter() - t1
+    set_threads(threads)
+    csu = len(comps) * n * n
+    return dict(value=csu * k / dt, unit="CSU/s", cores=threads, kind="oracle",
                 sample="%d full step(s) of the %dx%d ten-component field (FP64, OpenMP), %.1f s"
-                       % (k, n, n, dt))
+                       % (k, n, n, dt),
+                one_thread=dict(value=csu / dt1, unit="CSU/s",
+                                sample="1 full step on 1 thread, %.1f s" % dt1),
+                nproc=os.cpu_count(), cpu_model=cpu_model())
 
 
 def pmc_traffic(launch_alg_bytes):

@@ -69,6 +69,8 @@ def lib():
         L.oracle_step.argtypes = [pp, dp, dp]
         L.oracle_step.restype = ctypes.c_int
         L.oracle_run.argtypes = [pp, dp, ctypes.c_long]
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
         L.oracle_run.restype = ctypes.c_int
         L.oracle_fields.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         L.oracle_fields.restype = ctypes.c_int
@@ -241,3 +243,9 @@ def laplacian(lattice, phi):
     out = np.zeros(phi.shape)
     lib().oracle_laplacian(ctypes.byref(P), _dp(phi), _dp(out))
     return out
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (n <= 0: leave); returns the
+    previous count."""
+    return lib().oracle_set_threads(int(n))

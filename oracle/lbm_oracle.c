@@ -26,6 +26,7 @@
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -404,4 +405,12 @@ int oracle_fields(const oracle_params *P, const double *g, double *rho, double *
     if (F) memcpy(F, f.F, (size_t)P->N * 3 * ns * sizeof(double));
     fields_free(&f);
     return status;
+}
+
+/* Thread count of the OpenMP loops (for timing the oracle at 1 thread and
+ * at all cores); returns the count in effect before the call. */
+int oracle_set_threads(int n) {
+    int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
 }
