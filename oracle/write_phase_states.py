@@ -2,8 +2,9 @@
 workload starts from, computed by the oracle's own flash / Maxwell code.
 
 Run: ``python -m oracle.write_phase_states`` (from the repository root);
-``python -m oracle.write_phase_states ten_co2`` (or ``ternary_c1c2c3``, or
-``three_phase``) refreshes only that group of states.
+``python -m oracle.write_phase_states <group>`` (a key of ``PARTIAL``:
+``droplet_c1c2c3``, ``ten_co2``, ``ternary_c1c2c3``, ``three_phase``)
+refreshes only that group of states.
 Only ``oracle/`` and the seeded draws in ``inputs/`` are used; nothing comes
 from the GPU path.  All densities stored are lattice-unit MASS densities per
 component (rho_i = M_i rho~_i), in the lattice units of each workload's own
@@ -188,7 +189,18 @@ def three_phase_state():
                 rho_V=rho[0], rho_L1=rho[1], rho_L2=rho[2])
 
 
-PARTIAL = {"ten_co2": lambda st: st.update(ten_co2_states()),
+def droplet_c1c2c3_state():
+    """Section III.A: C1/C2/C3 (Table I, k_ij = 0) flashed at 250 K and 50 bar
+    with z = (0.5, 0.25, 0.25), the droplet system of the Young-Laplace
+    study."""
+    comps = [C.TABLE_I["C1"], C.TABLE_I["C2"], C.TABLE_I["C3"]]
+    st = two_phase_state(comps, 250.0, 50.0, [0.5, 0.25, 0.25])
+    st.update(components=comp_list(comps), T=250.0)
+    return st
+
+
+PARTIAL = {"droplet_c1c2c3": lambda st: st.update(droplet_c1c2c3=droplet_c1c2c3_state()),
+           "ten_co2": lambda st: st.update(ten_co2_states()),
            "ternary_c1c2c3": lambda st: st.update(ternary_c1c2c3=ternary_diagram_states()),
            "three_phase": lambda st: st.update(three_phase=three_phase_state())}
 
@@ -230,6 +242,7 @@ def main(only=None):
     states.update(ten_co2_states())
     states["ternary_c1c2c3"] = ternary_diagram_states()
     states["three_phase"] = three_phase_state()
+    states["droplet_c1c2c3"] = droplet_c1c2c3_state()
     path = Fi.PHASE_STATES
     with open(path, "w") as f:
         json.dump(states, f, indent=1)

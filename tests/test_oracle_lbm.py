@@ -205,6 +205,43 @@ def test_flat_interface_relaxes_to_maxwell_other_cubics(oracle_lib, eos):
     assert np.abs(fl["u"]).max() < 1e-9
 
 
+@pytest.mark.parametrize("eta", [0.1, 0.3])
+def test_linear_acoustics_frequency(oracle_lib, eta):
+    """A small density wave (amplitude 1e-6, wavelength 64) on a uniform
+    supercritical C1 state (250 K, b rt0 = eta): linearising Eq. (1)-(5)
+    about it gives an oscillator of frequency
+        w0^2 = (1/M) [ (dp/drt)_T k^2 + kappa rt0 k^4 ],
+    (continuity, momentum with the force -rt grad psi, and Gibbs-Duhem
+    rt dmu = dp), with k^2 the lattice Laplacian's symbol 4 sin^2(pi/64).
+    The wave's amplitude is fitted to A exp(-G t) cos(w t + phi) and
+    w0^2 = w^2 + G^2 must match within 1e-3.  This pins the pressure the
+    scheme carries: an equilibrium that kept c_s^2 rho, a wrong force sign
+    or a dropped kappa term fails it."""
+    from scipy.optimize import curve_fit
+    c1 = C.TABLE_I["C1"]
+    mix = lbm.oracle_mixture([c1], 250.0)
+    rt0 = eta / mix.pr.b[0]
+    M = mix.M[0]
+    n = 64
+    x = np.arange(n)
+    f = (M * rt0 * (1 + 1e-6 * np.cos(2 * np.pi * x / n))).reshape(1, 1, 1, n)
+    sim = lbm.OracleLBM(mix, 0, (n, 1), f)
+    amp = []
+    for _ in range(1500):
+        r = sim.rho().reshape(-1)
+        amp.append(np.sum((r - r.mean()) * np.cos(2 * np.pi * x / n)))
+        sim.run(1)
+    amp = np.array(amp) / amp[0]
+    h = 1e-7 * rt0
+    dpdr = (mix.pr.pressure_rho([rt0 + h]) - mix.pr.pressure_rho([rt0 - h])) / (2 * h)
+    k2 = 4 * np.sin(np.pi / n) ** 2
+    w_th = np.sqrt((dpdr * k2 + mix.sqk[0] ** 2 * rt0 * k2 ** 2) / M)
+    model = lambda t, A, G, w, ph: A * np.exp(-G * t) * np.cos(w * t + ph)
+    (A, G, w, ph), _ = curve_fit(model, np.arange(len(amp)), amp, p0=[1.0, 1e-3, w_th, 0.0])
+    assert G > 0
+    assert abs(np.sqrt(w * w + G * G) / w_th - 1) < 1e-3
+
+
 def test_d3q19_reduces_to_d2q9_on_a_one_dimensional_field(oracle_lib):
     """A field that varies along x only: D2Q9 and D3Q19 both reduce to the
     same three-velocity lattice along x (weights 2/3, 1/6, 1/6; the same
