@@ -3,6 +3,7 @@ thermodynamics (what the paper validates in Section III):
 
 * pure C1 flat interface -> Maxwell coexistence densities (Table II case 1),
   with the paper's PR and with SRK / vdW in its place;
+* Table II cases 1-6 on the paper's 400 x 2 set-up against Tables III-IV;
 * binary C1/C2 flat interface -> the flash tie line at the LBM's own
   pressure (two components at fixed T have one degree of freedom, so the
   bulk phases must sit on the flash at the measured p);
@@ -70,6 +71,66 @@ def test_flat_interface_reaches_maxwell(eos):
            umax=float(np.abs(out["u"]).max()))
     assert abs(eV) < 1e-5 and abs(eL) < 1e-5
     assert np.abs(out["u"]).max() < 1e-12
+
+
+def test_vle_cases_1_to_6_reproduce_tables_iii_and_iv():
+    """Section III.B as the paper runs it: Table II cases 1-6 (C1 ... C6,
+    equimolar, k_ij = 0), 400 x 2 slabs from Eq. (15) at the flash state,
+    10^6 steps, FP64 (one launch per case and step).  Bulk phases (16-column
+    windows) against the paper's own LBM results (Table III: densities
+    within 5e-4 relative, mole fractions within 2e-4), and against the flash
+    at the initial T and z and the LBM's vapour pressure, the comparison of
+    Table IV (paper: at most 0.265 %; here at most 0.3 %)."""
+    import json
+    import os
+    from oracle import thermo as th
+    from oracle.lbm import oracle_mixture
+    capi = _capi()
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(gold, "table_iii.json")) as f:
+        t3 = json.load(f)["cases"]
+    with open(os.path.join(gold, "table_iv.json")) as f:
+        t4 = json.load(f)["cases"]
+    n = 400
+    runs = []
+    for case in range(1, 7):
+        comps, T, _ = C.table_ii_components(case)
+        st = W.states()["vle%d" % case]
+        mix = capi.Mixture.from_components(comps, T)
+        sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (n, 2),
+                              Fi.slab(n, 2, st["rho_V"], st["rho_L"], st["S_V"]))
+        runs.append((case, comps, T, mix, sim))
+    capi.step_many([r[4] for r in runs], 1000000)
+    worst_t3_rho = worst_t3_x = worst_t4 = 0.0
+    for case, comps, T, mix, sim in runs:
+        assert sim.diagnostics()["rc"] == 0
+        om = oracle_mixture(comps, T)
+        rt = sim.read_moments(velocity=False)["rho"][:, 0, :, :] / om.M[:, None, None]
+        vap = np.concatenate([rt[:, :, 0:8], rt[:, :, n - 8:n]], axis=2).mean(axis=(1, 2))
+        liq = rt[:, :, n // 2 - 8:n // 2 + 8].mean(axis=(1, 2))
+        N = len(comps)
+        if N == 1:
+            _, rv, rl = th.maxwell(om.pr)
+            flash = {"V": (np.array([rv]), np.ones(1)), "L": (np.array([rl]), np.ones(1))}
+        else:
+            r = th.flash(om.pr, np.ones(N) / N, om.pr.pressure_rho(vap))
+            flash = {"V": (r.y * r.rhoV, r.y), "L": (r.x * r.rhoL, r.x)}
+        errs = {}
+        for ph, b in (("V", vap), ("L", liq)):
+            x = b / b.sum()
+            rho_kg = th.mass_density_si(comps, om.units.rho_molar_si(b))
+            worst_t3_rho = max(worst_t3_rho, abs(rho_kg / t3[str(case)][ph]["rho"] - 1))
+            worst_t3_x = max(worst_t3_x, float(np.max(np.abs(x - t3[str(case)][ph]["x"]))))
+            fr, fx = flash[ph]
+            e = [100 * abs((b @ om.M) / (fr @ om.M) - 1)] + list(100 * np.abs(x / fx - 1))
+            errs[ph] = [round(float(v), 6) for v in e]
+            worst_t4 = max(worst_t4, max(e))
+        report("vle_table_iv", case=case, errors_pct=errs, paper_pct=t4[str(case)])
+        sim.close()
+        mix.close()
+    report("vle_table_iii", rho_rel=worst_t3_rho, x_abs=worst_t3_x, table_iv_max_pct=worst_t4)
+    assert worst_t3_rho < 5e-4 and worst_t3_x < 2e-4
+    assert worst_t4 < 0.3
 
 
 def test_binary_flat_interface_on_flash_tie_line():
