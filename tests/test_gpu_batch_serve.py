@@ -4,9 +4,10 @@
   gives bitwise the same populations as stepping each simulation alone.
 * FP32 storage against FP64 on the same batch: bulk phase densities within
   1e-4 relative and mole fractions within 1e-3 absolute.
+* The full-size batched sweep, sampled instances against the oracle.
 * The server: every request's result is bitwise the same alone and in the
-  mix; the HBM budget is never exceeded; a request that goes non-finite
-  fails alone while the others finish normally.
+  mix and matches the oracle; the HBM budget is never exceeded; a request
+  that goes non-finite fails alone while the others finish normally.
 """
 import numpy as np
 import pytest
@@ -76,11 +77,62 @@ def test_fp32_batch_against_fp64_equilibrium_phases():
     b.close()
 
 
+def test_full_size_sweep_sampled_parity():
+    """The benchmark's batched sweep at full size (256 C1/C3/nC10 instances,
+    64^2 ... 256^2, FP32 storage, one launch per step as timed): after 20
+    batched steps, sampled instances (the first, a middle one, the largest
+    and the last) against the oracle run alone, every density within the
+    FP32-storage bar of 1e-4 relative."""
+    capi = _capi()
+    from paper_2306_10652_amd import batch
+    from oracle.lbm import OracleLBM, oracle_mixture
+    S = W.states()["ternary_sweep"]
+    specs = batch.ternary_specs(S)
+    sw = batch.Sweep(specs, capi.FP32_STORAGE)
+    sw.step(20)
+    big = int(np.argmax([np.prod(sp["shape"]) for sp in specs]))
+    worst = 0.0
+    for k in sorted({0, len(specs) // 2, big, len(specs) - 1}):
+        sp = specs[k]
+        o = OracleLBM(oracle_mixture(sp["comps"], sp["T"]), 0, sp["shape"], sp["rho"])
+        o.run(20)
+        g = sw.sims[k].read_moments(velocity=False)["rho"]
+        e = float(np.max(np.abs(g - o.rho()) / np.abs(o.rho())))
+        report("sweep_full_parity", instance=k, shape=sp["shape"], rho_rel=e)
+        worst = max(worst, e)
+    sw.close()
+    assert worst <= 1e-4
+
+
 def serving_requests(count=5, tol=1e-6, max_steps=4000):
     from paper_2306_10652_amd import serve
     reqs = serve.pool_requests(W.states()["serving_pool"], count, rate_hz=200.0, tol=tol,
                                max_steps=max_steps, max_n2d=96, max_n3d=20)
     return reqs
+
+
+def test_server_results_match_oracle():
+    """Requests served in the mix (D2Q9 and a D3Q19 one, FP32 storage,
+    batched with each other) against the oracle run alone for the same
+    number of steps: every density within 1e-4 relative."""
+    capi = _capi()
+    from paper_2306_10652_amd import serve
+    from oracle.lbm import OracleLBM, oracle_mixture
+    reqs = serve.pool_requests(W.states()["serving_pool"], 8, rate_hz=200.0, tol=1e-12,
+                               max_steps=200, max_n2d=64, max_n3d=16)
+    assert any(r.lattice == capi.D3Q19 for r in reqs)
+    srv = serve.Server(8 << 30, chunk=100, keep_fields=True)
+    done = srv.run(reqs)
+    worst = 0.0
+    for r in done:
+        assert r.status == 0 and r.steps == 200
+        o = OracleLBM(oracle_mixture(r.comps, r.T), r.lattice, r.shape, r.rho)
+        o.run(r.steps)
+        rho_o = o.rho()
+        e = float(np.max(np.abs(r.result["rho"] - rho_o) / np.abs(rho_o)))
+        report("serve_oracle", rid=r.rid, lattice=r.lattice, shape=r.shape, N=r.N, rho_rel=e)
+        worst = max(worst, e)
+    assert worst <= 1e-4
 
 
 def test_server_alone_equals_mix_and_budget():
