@@ -270,7 +270,7 @@ fuglbm_status build_items(fuglbm_sim *s) {
 }
 
 void drop_graph(fuglbm_sim *s) {
-    if (s->graph.exec) hipGraphExecDestroy(s->graph.exec);
+    if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
     s->graph = GraphCache{};
 }
 
@@ -295,8 +295,8 @@ fuglbm_status ensure_graph(fuglbm_sim *s) {
     for (int k = 0; k < GRAPH_STEPS; ++k) {
         hipError_t e = launch_one_step(s, k & 1, cs);
         if (e != hipSuccess) {
-            hipGraph_t g;
-            hipStreamEndCapture(cs, &g);
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(cs, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
             return hip_fail(e, "capture");
         }
     }
@@ -304,7 +304,7 @@ fuglbm_status ensure_graph(fuglbm_sim *s) {
     HIP_TRY(hipStreamEndCapture(cs, &g));
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     s->graph.exec = ex;
     s->graph.steps = GRAPH_STEPS;
@@ -342,8 +342,8 @@ struct Timer {
         if (hipEventCreate(&b) != hipSuccess) b = nullptr;
     }
     ~Timer() {
-        if (a) hipEventDestroy(a);
-        if (b) hipEventDestroy(b);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
     }
     bool ok() const { return a && b; }
 };
@@ -633,7 +633,7 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     }
     fuglbm_status rc = FUGLBM_OK;
     auto bail = [&](fuglbm_status r) {
-        if (s->owned) hipFree(s->base);
+        if (s->owned) (void)hipFree(s->base);
         delete s;
         return r;
     };
@@ -907,10 +907,10 @@ void forget_sim_in_batches(const fuglbm_sim *s);
 
 void fuglbm_destroy_sim(fuglbm_sim *s) {
     if (!s) return;
-    hipStreamSynchronize(s->last_stream);
+    (void)hipStreamSynchronize(s->last_stream);
     forget_sim_in_batches(s);
     drop_graph(s);
-    if (s->owned) hipFree(s->base);
+    if (s->owned) (void)hipFree(s->base);
     delete s;
 }
 
@@ -947,15 +947,15 @@ fuglbm_status batch_graph(BatchTable &bt, int ncomp, bool fp32) {
         hipError_t e =
             launch_fused(bt.kernel, ncomp, fp32, bt.ditems, bt.nitems, bt.dsims, k & 1, cs);
         if (e != hipSuccess) {
-            hipGraph_t g;
-            hipStreamEndCapture(cs, &g);
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(cs, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
             return hip_fail(e, "batch capture");
         }
     }
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamEndCapture(cs, &g));
     hipError_t e = hipGraphInstantiate(&bt.graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         bt.graph = nullptr;
         return hip_fail(e, "hipGraphInstantiate (batch)");
@@ -974,7 +974,7 @@ fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group
                           int rows = 0, int kernel = 0) {
     HIP_TRY(hipStreamSynchronize(st));  // the old table may still be read by queued launches
     if (bt.graph) {
-        hipGraphExecDestroy(bt.graph);
+        (void)hipGraphExecDestroy(bt.graph);
         bt.graph = nullptr;
     }
     bt.kernel = kernel ? kernel : group[0]->kernel;
@@ -1004,12 +1004,12 @@ fuglbm_status build_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group
         if (li < n) items[b] = logical[li];
     }
     if (hs.size() > bt.cap_sims) {
-        if (bt.dsims) hipFree(bt.dsims);
+        if (bt.dsims) (void)hipFree(bt.dsims);
         bt.cap_sims = hs.size() * 2;
         HIP_TRY(hipMalloc(&bt.dsims, bt.cap_sims * sizeof(FusedSim)));
     }
     if (items.size() > bt.cap_items) {
-        if (bt.ditems) hipFree(bt.ditems);
+        if (bt.ditems) (void)hipFree(bt.ditems);
         bt.cap_items = items.size() * 2;
         HIP_TRY(hipMalloc(&bt.ditems, bt.cap_items * sizeof(FusedItem)));
     }
@@ -1092,7 +1092,7 @@ void forget_sim_in_batches(const fuglbm_sim *s) {
         for (size_t k = 0; k < bt.sims.size(); ++k) {
             if (bt.sims[k] == s && bt.uids[k] == s->uid) {
                 if (bt.graph) {
-                    hipGraphExecDestroy(bt.graph);
+                    (void)hipGraphExecDestroy(bt.graph);
                     bt.graph = nullptr;
                 }
                 bt.sims.clear();
