@@ -133,6 +133,45 @@ def test_vle_cases_1_to_6_reproduce_tables_iii_and_iv():
     assert worst_t4 < 0.3
 
 
+@pytest.mark.parametrize("eos", ["SRK", "vdW"])
+def test_other_cubics_ternary_slab_on_their_flash(eos):
+    """Table II case 3 (C1/C2/C3, 250 K, 35 bar, equimolar) with SRK or vdW
+    in place of PR: a 400 x 2 slab started from that EOS's own flash, 10^6
+    steps, FP64.  The bulk phases have equal fugacities (Eq. (12) for the
+    chosen cubic) and lie on that EOS's flash at the LBM's vapour pressure
+    and the initial z within 0.3 % (the Table IV comparison)."""
+    from oracle import thermo as th
+    from oracle.lbm import oracle_mixture
+    capi = _capi()
+    comps, T, p = C.table_ii_components(3)
+    om = oracle_mixture(comps, T, eos=eos)
+    N = len(comps)
+    z = np.ones(N) / N
+    r0 = th.flash(om.pr, z, om.units.p(p * th.BAR))
+    assert r0.two_phase
+    vV, vL = 1.0 / r0.rhoV, 1.0 / r0.rhoL
+    S_V = r0.beta * vV / (r0.beta * vV + (1.0 - r0.beta) * vL)
+    n = 400
+    rho = Fi.slab(n, 2, om.M * r0.y * r0.rhoV, om.M * r0.x * r0.rhoL, S_V)
+    mix = capi.Mixture.from_components(comps, T, eos=eos)
+    sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (n, 2), rho)
+    sim.step_n(1000000)
+    assert sim.diagnostics()["rc"] == 0
+    rt = sim.read_moments(velocity=False)["rho"][:, 0, :, :] / om.M[:, None, None]
+    vap = np.concatenate([rt[:, :, 0:8], rt[:, :, n - 8:n]], axis=2).mean(axis=(1, 2))
+    liq = rt[:, :, n // 2 - 8:n // 2 + 8].mean(axis=(1, 2))
+    dlnf = float(np.max(np.abs(om.pr.ln_fugacity_rho(liq) - om.pr.ln_fugacity_rho(vap))))
+    r = th.flash(om.pr, z, om.pr.pressure_rho(vap))
+    err = 0.0
+    for b, fr, fx in ((vap, r.y * r.rhoV, r.y), (liq, r.x * r.rhoL, r.x)):
+        err = max(err, abs((b @ om.M) / (fr @ om.M) - 1), float(np.max(np.abs((b / b.sum()) / fx - 1))))
+    report("cubic_slab", eos=eos, dlnf=dlnf, table_iv_max_pct=100 * err)
+    sim.close()
+    mix.close()
+    assert dlnf < 1e-4
+    assert 100 * err < 0.3
+
+
 def test_binary_flat_interface_on_flash_tie_line():
     from oracle import thermo as th
     from oracle.lbm import oracle_mixture
