@@ -62,6 +62,38 @@ def test_bitwise_determinism_and_batched_equals_single():
         assert np.array_equal(s.read_populations(), ref)
 
 
+def test_heterogeneous_batch_and_degenerate_calls():
+    """One step_many call over simulations that differ in component count,
+    precision and lattice (grouped into one launch per (N, precision) for
+    D2Q9, stepped alone for D3Q19): each ends bitwise where stepping it
+    alone ends.  Degenerate calls: zero steps and an empty batch change
+    nothing; a repeated simulation or negative steps are EINVAL."""
+    capi = _capi()
+    cases = [(W.random_droplet(3, (67, 45), seed=1), 0), (W.random_droplet(3, (40, 33), seed=2), 0),
+             (W.random_droplet(3, (50, 50), seed=3), 1), (W.random_droplet(5, (61, 29), seed=4), 0),
+             (W.random_droplet(2, (9, 8, 7), seed=5, lattice=1), 0),
+             (W.random_droplet(2, (9, 8, 7), seed=6, lattice=1), 1)]
+    alone = []
+    for wl, prec in cases:
+        s = make(wl, prec, capi=capi)
+        s.step_n(41)
+        alone.append(s.read_populations())
+    sims = [make(wl, prec, capi=capi) for wl, prec in cases]
+    g0 = [s.read_populations() for s in sims]
+    capi.step_many(sims, 0)
+    capi.step_many([], 10)
+    for s in sims:
+        s.step_n(0)
+    for s, g in zip(sims, g0):
+        assert np.array_equal(s.read_populations(), g)
+    capi.step_many(sims, 41)
+    for s, ref in zip(sims, alone):
+        assert np.array_equal(s.read_populations(), ref)
+        assert s.diagnostics()["step"] == 41
+    assert capi.fuglbm_step_many([sims[0], sims[1], sims[0]], 5) == 1
+    assert capi.fuglbm_step_many(sims[:2], -1) == 1
+
+
 def test_fused_and_generic_kernels_agree():
     wl = W.random_droplet(5, (93, 40), seed=9)
     a = make(wl)
