@@ -168,6 +168,36 @@ def test_d3q19_fp32_storage():
     assert e <= 1e-5
 
 
+_D3_BIG = {}
+
+
+def _d3q19_big_reference():
+    """128^3 ten-component D3Q19 field and the oracle's densities after 2
+    steps (computed once per session: the oracle needs ~20 s for it)."""
+    if not _D3_BIG:
+        wl = W.random_droplet(10, (128, 128, 128), seed=12, lattice=1, noise=1e-3)
+        o = wl.oracle()
+        assert o.run(2) == 0
+        _D3_BIG.update(wl=wl, rho=o.rho())
+        del o
+    return _D3_BIG["wl"], _D3_BIG["rho"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_d3q19_largest_serving_size(precision):
+    """The largest D3Q19 request of the serving workload: 128^3 with ten
+    components (6.4 GB of FP64 populations on the GPU), 2 steps against the
+    oracle over the whole field (FP64 <= 1e-12, FP32 storage <= 1e-6)."""
+    _capi()
+    wl, ref = _d3q19_big_reference()
+    g = run_gpu(wl, 2, precision=precision)
+    e = rel_err(g["rho"], ref)
+    report("d3q19_128", precision=precision, rho_rel=e)
+    g["sim"].close()
+    assert g["status"] == 0
+    assert e <= (1e-12 if precision == 0 else 1e-6)
+
+
 def test_spinodal10_full_size_fp64():
     """1024 x 1024, ten components, seeded kij: 3 steps of the fused kernel in
     its benchmark launch configuration (variant and rows as the autotuner
