@@ -280,7 +280,7 @@ hipError_t launch_one_step(fuglbm_sim *s, int flip_parity, hipStream_t st) {
                             st);
     return launch_step_generic(s->lattice, s->fp32, s->dc, s->N, s->nx, s->ny, s->nz, s->buf[flip_parity],
                                s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
-                               s->u_f, s->status, st);
+                               s->u_f, s->status, s->hc.omega != 1.0, st);
 }
 
 constexpr int GRAPH_STEPS = 32;  // even: a replay returns to the same parity

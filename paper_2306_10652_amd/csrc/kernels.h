@@ -24,10 +24,11 @@ constexpr int FUSED_OUT = 60;  // output columns per strip (2-column halo each s
 
 hipError_t launch_init(int lattice, bool fp32, const SimConst *c, int64_t ns, const double *rho,
                        void *g, hipStream_t st);
+// keep_old: tau != 1, the collision reads the old populations
 hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int ncomp, int nx, int ny,
                                int nz, const void *gs, void *gd, double *rho_f, double *psi_f,
                                double *s_f, double *j_f, double *u_f, uint32_t *status,
-                               hipStream_t st);
+                               bool keep_old, hipStream_t st);
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
                          double *rho_f, double *psi_f, double *s_f, double *j_f, double *u_f,
                          uint32_t *status, hipStream_t st);

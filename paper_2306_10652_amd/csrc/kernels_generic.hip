@@ -187,26 +187,69 @@ __device__ __forceinline__ void site_velocity(const SimConst *c, int64_t s, cons
 }
 
 // ---- LDS-tiled force, velocity and collision --------------------------------
-// A workgroup owns a tile of TX x TY x TZ sites (one thread per site) and,
-// one component at a time, stages psi_i and rho_i over the tile plus a
-// one-site halo in LDS, so every neighbour value is read from HBM/L2 once
-// per tile instead of once per neighbour.
-template <class L> struct Tile;
-template <> struct Tile<D2Q9> { static constexpr int TX = 64, TY = 4, TZ = 1, HZ = 0; };
-template <> struct Tile<D3Q19> { static constexpr int TX = 16, TY = 4, TZ = 4, HZ = 1; };
+// A workgroup owns a tile of TX x TY x TZ sites (one thread per site) and
+// stages psi_i (and rho_i) over the tile plus a one-site halo in LDS, so
+// every neighbour value is read from HBM/L2 once per tile instead of once
+// per neighbour.
+//
+// Collision tiles are 64 sites wide: a wavefront covers 64 consecutive x
+// sites of one row, so each of its population stores is one 512 B (FP64) /
+// 256 B (FP32) run.  The velocity pass only reads, and takes the shape with
+// the smallest halo.
+//
+// Tiles are numbered x-fastest (collision units: collide_unit), and each
+// XCD takes a contiguous range of work units
+// (workgroups go to the XCDs round-robin).  The units that write a lattice
+// row's blocks and the partly written cache lines at tile edges then run
+// at the same time on the same L2, and the pages being written at any
+// moment are few.
+template <class L> struct TileC;
+template <> struct TileC<D2Q9> { static constexpr int TX = 64, TY = 4, TZ = 1, HZ = 0; };
+template <> struct TileC<D3Q19> { static constexpr int TX = 64, TY = 2, TZ = 2, HZ = 1; };
+template <class L> struct TileV;
+template <> struct TileV<D2Q9> { static constexpr int TX = 64, TY = 4, TZ = 1, HZ = 0; };
+template <> struct TileV<D3Q19> { static constexpr int TX = 16, TY = 4, TZ = 4, HZ = 1; };
+constexpr int TILE_XCDS = 8;
 
-template <class L>
+// This workgroup's work unit; gridDim.x is a multiple of TILE_XCDS
+// (unit_blocks), units at or past the real count are padding.
+__device__ __forceinline__ int xcd_unit() {
+    const int per = (int)gridDim.x / TILE_XCDS;
+    return (int)(blockIdx.x % TILE_XCDS) * per + (int)(blockIdx.x / TILE_XCDS);
+}
+
+inline unsigned unit_blocks(int64_t units) {
+    return (unsigned)((units + TILE_XCDS - 1) / TILE_XCDS * TILE_XCDS);
+}
+
+// Collision work unit -> (tile, component).  Units go through the tiles in
+// chunks of COLLIDE_CHUNK, each chunk component by component, so the
+// tiles that read one another's halos run together while the rows being
+// written stay few.
+constexpr int COLLIDE_CHUNK = 32;
+__device__ __forceinline__ void collide_unit(int unit, int ntiles, int N, int &tile, int &comp) {
+    const int t0 = unit / (COLLIDE_CHUNK * N) * COLLIDE_CHUNK;
+    const int kk = min(COLLIDE_CHUNK, ntiles - t0);
+    const int r = unit - t0 * N;
+    comp = r / kk;
+    tile = t0 + r % kk;
+}
+
+template <class L, class S>
 struct TileGeom {
-    static constexpr int TX = Tile<L>::TX, TY = Tile<L>::TY, TZ = Tile<L>::TZ, HZ = Tile<L>::HZ;
+    static constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, HZ = S::HZ;
     static constexpr int HX = TX + 2, HY = TY + 2, HZN = TZ + 2 * HZ;
     static constexpr int NH = HX * HY * HZN;   // halo tile points
     static_assert(TX * TY * TZ == TPB, "one thread per tile site");
     int x0, y0, z0, lx, ly, lz, x, y, z;
     bool active;
-    int lc;   // LDS index of this thread's site
-    __device__ TileGeom(const SimConst *c) {
+    int lc;      // LDS index of this thread's site
+    __host__ __device__ static int64_t count(int nx, int ny, int nz) {
+        return (int64_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ);
+    }
+    // tile b < count(nx, ny, nz), numbered x-fastest
+    __device__ TileGeom(const SimConst *c, int b) {
         const int ntx = (c->nx + TX - 1) / TX, nty = (c->ny + TY - 1) / TY;
-        const int b = blockIdx.x;
         x0 = (b % ntx) * TX;
         y0 = ((b / ntx) % nty) * TY;
         z0 = (b / (ntx * nty)) * TZ;
@@ -221,15 +264,19 @@ struct TileGeom {
         lc = ((lz + HZ) * HY + (ly + 1)) * HX + (lx + 1);
     }
     __device__ static int lds_off(int a) { return (L::ez(a) * HY + L::ey(a)) * HX + L::ex(a); }
+    // periodic image of v >= -1 (a tile can be wider than the grid)
+    __device__ static int wrap(int v, int n) {
+        v = v < 0 ? v + n : v;
+        while (v >= n) v -= n;
+        return v;
+    }
     // stage field f (one component plane of ns values) into lds[NH]
     __device__ void stage(const SimConst *c, const double *f, double *lds) const {
         const int nx = c->nx, ny = c->ny, nz = c->nz;
         for (int k = threadIdx.x; k < NH; k += TPB) {
             const int hx = k % HX, hy = (k / HX) % HY, hz = k / (HX * HY);
-            int gx = (x0 - 1 + hx) % nx, gy = (y0 - 1 + hy) % ny, gz = (z0 - HZ + hz) % nz;
-            if (gx < 0) gx += nx;
-            if (gy < 0) gy += ny;
-            if (gz < 0) gz += nz;
+            const int gx = wrap(x0 - 1 + hx, nx), gy = wrap(y0 - 1 + hy, ny),
+                      gz = wrap(z0 - HZ + hz, nz);
             lds[k] = f[(int64_t)gx + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz)];
         }
     }
@@ -244,13 +291,6 @@ struct TileGeom {
     }
 };
 
-inline unsigned tile_blocks(int lattice, int nx, int ny, int nz) {
-    const int TX = lattice == 0 ? Tile<D2Q9>::TX : Tile<D3Q19>::TX;
-    const int TY = lattice == 0 ? Tile<D2Q9>::TY : Tile<D3Q19>::TY;
-    const int TZ = lattice == 0 ? Tile<D2Q9>::TZ : Tile<D3Q19>::TZ;
-    return (unsigned)(((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ));
-}
-
 // u = (j + F/2) / rho, F = sum_i F_i, F_i = -rt_i grad psi_i  -> u_f
 template <class L>
 __global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__ c,
@@ -258,8 +298,12 @@ __global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__
                                                     const double *__restrict__ psi_f,
                                                     const double *__restrict__ j_f,
                                                     double *__restrict__ u_f) {
-    __shared__ double lp[TileGeom<L>::NH];
-    const TileGeom<L> T(c);
+    using TG = TileGeom<L, TileV<L>>;
+    __shared__ double lp[TG::NH];
+    const int unit = xcd_unit();
+    // padding units leave as a whole workgroup, before any barrier
+    if (unit >= TG::count(c->nx, c->ny, c->nz)) return;
+    const TG T(c, unit);
     const int64_t ns = c->nsites;
     const int64_t s = T.active ? (int64_t)T.x + (int64_t)c->nx * ((int64_t)T.y + (int64_t)c->ny * T.z) : 0;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, rhot = 0.0;
@@ -284,18 +328,28 @@ __global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__
     if (L::D == 3) u_f[2 * ns + s] = (j_f[2 * ns + s] + 0.5 * Fz) / rhot;
 }
 
-// collision (Eq. (1a)-(1c)) and push of component blockIdx.y; u from u_f
-template <class L, typename ST>
+// collision (Eq. (1a)-(1c)) and push of one component over one tile
+// (collide_unit); u from u_f
+// KEEP: tau != 1, so the collision keeps (1 - omega) g of the old population.
+template <class L, typename ST, bool KEEP>
 __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ c,
                                                    const void *__restrict__ gs, void *__restrict__ gd,
                                                    const double *__restrict__ rho_f,
                                                    const double *__restrict__ psi_f,
                                                    const double *__restrict__ u_f) {
-    __shared__ double lp[TileGeom<L>::NH];
-    __shared__ double lr[TileGeom<L>::NH];
-    const TileGeom<L> T(c);
+    using TG = TileGeom<L, TileC<L>>;
+    __shared__ double lp[TG::NH];
+    __shared__ double lr[TG::NH];
+    const int N = c->N;
+    const int unit = xcd_unit();
+    // padding units leave as a whole workgroup, before any barrier
+    const int ntiles = (int)TG::count(c->nx, c->ny, c->nz);
+    if (unit >= ntiles * N) return;
+    int tile, i;
+    collide_unit(unit, ntiles, N, tile, i);
+    const TG T(c, tile);
     const int64_t ns = c->nsites;
-    const int nx = c->nx, ny = c->ny, nz = c->nz, N = c->N;
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
     const int64_t s = T.active ? (int64_t)T.x + (int64_t)nx * ((int64_t)T.y + (int64_t)ny * T.z) : 0;
     const PopLayout<ST> P(N, L::Q, nx, (int64_t)ny * nz);
     const int64_t row = (int64_t)T.y + (int64_t)ny * T.z;
@@ -309,7 +363,6 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
     const double omega = c->omega, fcoef = c->fcoef;
     const char *gsb = (const char *)gs;
     char *gdb = (char *)gd;
-    const int i = blockIdx.y;
     {
         T.stage(c, psi_f + (int64_t)i * ns, lp);
         T.stage(c, rho_f + (int64_t)i * ns, lr);
@@ -327,13 +380,9 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
         // goes into the rest population, which stays at this site.  At
         // tau = 1 the collision does not depend on the old populations
         // (their moments came from the first pass): they are not read.
-        const bool keep_g = omega != 1.0;
         double err = 0.0;
-        // directions in a rolled loop: unrolled, the compiler hoists every
-        // load and the kernel needs 256 registers (one wavefront per SIMD)
-#pragma unroll 2
-        for (int a = 1; a < L::Q; ++a) {
-            const double gv = keep_g ? (double)*(const ST *)(gsb + P.move(row, i, a, T.x)) : 0.0;
+        auto dir = [&](int a) {
+            const double gv = KEEP ? (double)*(const ST *)(gsb + P.move(row, i, a, T.x)) : 0.0;
             const double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu,
                                             Gu, omega, fcoef);
             const ST v = (ST)o;
@@ -343,8 +392,19 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
             yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
             zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
             *(ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)) = v;
+        };
+        if constexpr (KEEP) {
+            // rolled: unrolled, the compiler hoists every load and the
+            // kernel needs 256 registers (one wavefront per SIMD)
+#pragma unroll 2
+            for (int a = 1; a < L::Q; ++a) dir(a);
+        } else {
+            // no loads: unrolled, the lattice vectors, weights and
+            // destination rows fold to constants per direction
+#pragma unroll
+            for (int a = 1; a < L::Q; ++a) dir(a);
         }
-        const double g0 = keep_g ? *(const double *)(gsb + P.rest(row, i, T.x)) : 0.0;
+        const double g0 = KEEP ? *(const double *)(gsb + P.rest(row, i, T.x)) : 0.0;
         const double o0 = collide_one<L>(0, g0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
                                          omega, fcoef);
         *(double *)(gdb + P.rest(row, i, T.x)) = sizeof(ST) == 4 ? o0 - err : o0;
@@ -437,15 +497,21 @@ inline unsigned nblocks(int64_t ns) { return (unsigned)((ns + TPB - 1) / TPB); }
 template <class L, typename ST>
 hipError_t step_generic_t(const SimConst *c, int ncomp, int64_t ns, int nx, int ny, int nz,
                           const void *gs, void *gd, double *rho_f, double *psi_f, double *s_f,
-                          double *j_f, double *u_f, uint32_t *status, hipStream_t st) {
+                          double *j_f, double *u_f, uint32_t *status, bool keep,
+                          hipStream_t st) {
     const unsigned nb = nblocks(ns);
-    const unsigned tb = tile_blocks(L::D == 2 ? 0 : 1, nx, ny, nz);
+    const unsigned vb = unit_blocks(TileGeom<L, TileV<L>>::count(nx, ny, nz));
+    const unsigned cb = unit_blocks(TileGeom<L, TileC<L>>::count(nx, ny, nz) * ncomp);
     hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, gs, rho_f, psi_f,
                        s_f, j_f, status);
     hipLaunchKernelGGL((k_interface<L>), dim3(nb), dim3(TPB), 0, st, c, s_f, psi_f);
-    hipLaunchKernelGGL((k_velocity_t<L>), dim3(tb), dim3(TPB), 0, st, c, rho_f, psi_f, j_f, u_f);
-    hipLaunchKernelGGL((k_collide_t<L, ST>), dim3(tb, ncomp), dim3(TPB), 0, st, c, gs, gd, rho_f,
-                       psi_f, u_f);
+    hipLaunchKernelGGL((k_velocity_t<L>), dim3(vb), dim3(TPB), 0, st, c, rho_f, psi_f, j_f, u_f);
+    if (keep)
+        hipLaunchKernelGGL((k_collide_t<L, ST, true>), dim3(cb), dim3(TPB), 0, st, c, gs, gd,
+                           rho_f, psi_f, u_f);
+    else
+        hipLaunchKernelGGL((k_collide_t<L, ST, false>), dim3(cb), dim3(TPB), 0, st, c, gs, gd,
+                           rho_f, psi_f, u_f);
     return hipGetLastError();
 }
 
@@ -481,13 +547,14 @@ hipError_t launch_init(int lattice, bool fp32, const SimConst *c, int64_t ns, co
 hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int ncomp, int nx, int ny,
                                int nz, const void *gs, void *gd, double *rho_f, double *psi_f,
                                double *s_f, double *j_f, double *u_f, uint32_t *status,
-                               hipStream_t st) {
+                               bool keep_old, hipStream_t st) {
     const int64_t ns = (int64_t)nx * ny * nz;
+    const bool k = keep_old;
     if (lattice == 0)
-        return fp32 ? step_generic_t<D2Q9, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st)
-                    : step_generic_t<D2Q9, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st);
-    return fp32 ? step_generic_t<D3Q19, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st)
-                : step_generic_t<D3Q19, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, st);
+        return fp32 ? step_generic_t<D2Q9, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st)
+                    : step_generic_t<D2Q9, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
+    return fp32 ? step_generic_t<D3Q19, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st)
+                : step_generic_t<D3Q19, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
 }
 
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
