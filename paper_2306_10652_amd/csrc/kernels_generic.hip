@@ -381,10 +381,38 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
         // tau = 1 the collision does not depend on the old populations
         // (their moments came from the first pass): they are not read.
         double err = 0.0;
+        // tau = 1: collide_one for a moving direction with the site's terms
+        // taken out of the direction loop: g^eq_a - w_a rho = w_a rho sq_a and
+        // F_a / w_a = 3 eF + 9 eu eF + 3 eu eG + K, where K depends on |e_a|^2
+        // only (weight classes |e|^2 = 1 and 2); the dot products with e_a
+        // add only its non-zero components (0 * u is not folded away)
+        const double c0 = -1.5 * uu;
+        const double K1 = -3.0 * Fu - Gu + 0.5 * (3.0 - (double)L::D) * Gu;
+        const double K2 = -3.0 * Fu - Gu + 0.5 * (6.0 - (double)L::D) * Gu;
+        const double A1 = omega * L::w(1) * r, A2 = omega * L::w(L::Q - 1) * r;
+        const double B1 = fcoef * L::w(1), B2 = fcoef * L::w(L::Q - 1);
+        auto edot = [](int a, double x, double y, double z) {
+            const int cx = L::ex(a), cy = L::ey(a), cz = L::ez(a);
+            const double tx = cx > 0 ? x : -x, ty = cy > 0 ? y : -y, tz = cz > 0 ? z : -z;
+            if (cx != 0) return cy != 0 ? tx + ty : (cz != 0 ? tx + tz : tx);
+            return cy != 0 ? (cz != 0 ? ty + tz : ty) : tz;
+        };
         auto dir = [&](int a) {
-            const double gv = KEEP ? (double)*(const ST *)(gsb + P.move(row, i, a, T.x)) : 0.0;
-            const double o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu,
-                                            Gu, omega, fcoef);
+            double o;
+            if constexpr (KEEP) {
+                const double gv = (double)*(const ST *)(gsb + P.move(row, i, a, T.x));
+                o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
+                                   omega, fcoef);
+            } else {
+                const double eu = edot(a, ux, uy, uz);
+                const double eF = edot(a, Fx, Fy, Fz);
+                const double eG = edot(a, Gx, Gy, Gz);
+                const bool e1 = L::ex(a) * L::ex(a) + L::ey(a) * L::ey(a) +
+                                L::ez(a) * L::ez(a) == 1;
+                const double sq = fma(eu, fma(4.5, eu, 3.0), c0);
+                const double q = fma(eF, fma(9.0, eu, 3.0), fma(3.0 * eu, eG, e1 ? K1 : K2));
+                o = fma(e1 ? A1 : A2, sq, (e1 ? B1 : B2) * q);
+            }
             const ST v = (ST)o;
             if (sizeof(ST) == 4) err += (double)v - o;
             int xx = T.x + L::ex(a), yy = T.y + L::ey(a), zz = T.z + L::ez(a);
