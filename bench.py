@@ -223,6 +223,44 @@ def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=No
     return st
 
 
+def d3q19_leg(n=128, steps=100, warmup=10):
+    """The largest D3Q19 request of the serving stream: the ten-component
+    spinodal mixture on a n^3 periodic grid (uniform, +-1 % noise), FP64
+    and FP32 storage, multi-pass path.  Kernel time from HIP events on the
+    library's stream; traffic per step both as the populations alone (the
+    headline's definition) and with the fields the passes exchange."""
+    import torch
+    from paper_2306_10652_amd import capi
+    from inputs import components as C
+    from inputs import fields as Fi
+    st = Fi.load_phase_states()["spinodal10"]
+    rho = Fi.add_noise(Fi.uniform(n, n, st["rho_uniform"], nz=n), 1e-2, 4)
+    mix = capi.Mixture.from_components(C.N_ALKANES, 325.0, np.array(st["kij"]),
+                                       kappa_ref=0.02, tau=1.0)
+    N, ns = mix.N, n ** 3
+    stream = torch.cuda.Stream()
+    out = dict(grid=[n, n, n], components=N, lattice="D3Q19", steps=steps)
+    for prec, name in ((capi.FP64, "fp64"), (capi.FP32_STORAGE, "fp32_storage")):
+        sim = capi.Simulation(mix, capi.D3Q19, prec, (n, n, n), rho, stream=stream)
+        sim.step_n(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step_n(steps)
+        e1.record(stream)
+        e1.synchronize()
+        s = e0.elapsed_time(e1) * 1e-3 / steps
+        pop = sim.info()["alg_bytes_per_step"]
+        fields = (8 * N + 14) * 8 * ns
+        out[name] = dict(ms_per_step=round(s * 1e3, 4), value=round(N * ns / s, 1), unit="CSU/s",
+                         populations_gbs=round(pop / s / 1e9, 1),
+                         with_fields_gbs=round((pop + fields) / s / 1e9, 1),
+                         status=sim.diagnostics()["status"])
+        sim.close()
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -285,8 +323,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the sweep, time-vs-N and serving legs")
-    ap.add_argument("--legs", default="sweep,time_vs_n,serving",
-                    help="comma-separated extra legs to run (sweep, time_vs_n, serving)")
+    ap.add_argument("--legs", default="sweep,time_vs_n,serving,d3q19",
+                    help="comma-separated extra legs to run (sweep, time_vs_n, serving, "
+                         "d3q19)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
     ap.add_argument("--rows", type=int, default=0,
@@ -357,6 +396,8 @@ def main():
     if "serving" in legs:
         cap = out["batched_sweep"]["fp32_batched"]["value"] if "batched_sweep" in out else None
         out["serving"] = serving_leg(capacity_csu_s=cap)
+    if "d3q19" in legs:
+        out["d3q19"] = d3q19_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_budget)
     print(json.dumps(out), flush=True)
