@@ -1,6 +1,6 @@
 // Multi-pass step for any lattice (D2Q9, D3Q19), FP64 or FP32 storage
 // (population layout: PopLayout of the common header):
-//   pass 1  moments + local PR fugacity: rho_i, RT ln f_i, s = sum sqrt(kappa_j) rt_j, j
+//   pass 1  moments + local cubic-EOS fugacity: rho_i, RT ln f_i, s = sum sqrt(kappa_j) rt_j, j
 //   pass 2  psi_i = RT ln f_i - sqrt(kappa_i) lap(s)             (Eq. (4)-(5))
 //   pass 3  u = (j + F/2) / rho, F = -sum_i rt_i grad psi_i      (LDS tiles)
 //   pass 4  F_i, G_i = grad rho_i, collide (Eq. (1)), push        (LDS tiles)
