@@ -36,6 +36,13 @@
  *    Arithmetic is FP64 in both precisions.  Host-side population arrays
  *    (read/write_populations) are [ncomp][Q][sites] FP64, site = x +
  *    nx*(y + ny*z).
+ *  - Direction order a (lattice vector e_a):
+ *    D2Q9   0 (0,0); 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1); 5 (1,1);
+ *           6 (-1,1); 7 (-1,-1); 8 (1,-1).
+ *    D3Q19  0 (0,0,0); faces 1 (1,0,0); 2 (-1,0,0); 3 (0,1,0); 4 (0,-1,0);
+ *           5 (0,0,1); 6 (0,0,-1); edges 7 (1,1,0); 8 (-1,-1,0);
+ *           9 (1,-1,0); 10 (-1,1,0); 11 (1,0,1); 12 (-1,0,-1); 13 (1,0,-1);
+ *           14 (-1,0,1); 15 (0,1,1); 16 (0,-1,-1); 17 (0,1,-1); 18 (0,-1,1).
  */
 #ifndef FUGLBM_H
 #define FUGLBM_H
