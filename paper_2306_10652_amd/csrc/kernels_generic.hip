@@ -512,7 +512,7 @@ __global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
         red[threadIdx.x] = v;
         __syncthreads();
         for (int w = TPB / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
         if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nq + q] = red[0];
@@ -595,7 +595,7 @@ hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, 
                 : fields_generic_t<D3Q19, double>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st);
 }
 
-hipError_t launch_diag(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
+hipError_t launch_diag(int lattice, bool fp32, const SimConst *c, int64_t /*ns*/, const void *g,
                        double *snap, double *part, int nblk, int use_snap, hipStream_t st) {
     if (lattice == 0) {
         if (fp32) hipLaunchKernelGGL((k_diag<D2Q9, float>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
