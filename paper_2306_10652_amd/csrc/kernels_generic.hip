@@ -270,14 +270,59 @@ struct TileGeom {
         while (v >= n) v -= n;
         return v;
     }
-    // stage field f (one component plane of ns values) into lds[NH]
+    // stage field f (one component plane of ns values) into lds[NH]; each
+    // thread issues all of its loads before its first LDS write, so the
+    // loads are in flight together
     __device__ void stage(const SimConst *c, const double *f, double *lds) const {
         const int nx = c->nx, ny = c->ny, nz = c->nz;
-        for (int k = threadIdx.x; k < NH; k += TPB) {
-            const int hx = k % HX, hy = (k / HX) % HY, hz = k / (HX * HY);
-            const int gx = wrap(x0 - 1 + hx, nx), gy = wrap(y0 - 1 + hy, ny),
-                      gz = wrap(z0 - HZ + hz, nz);
-            lds[k] = f[(int64_t)gx + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz)];
+        if constexpr (TX == 64) {
+            // a wavefront stages whole halo rows (HX = 66 x sites): one
+            // y/z wrap per row, one wrapped x per lane for all rows
+            constexpr int NW = TPB / 64;
+            const int lane = threadIdx.x & 63;
+            const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            const int gx0 = wrap(x0 - 1 + lane, nx);
+            const int gx1 = wrap(x0 + 63 + (lane & 1), nx);   // halo x = 64, 65
+            constexpr int NR = (HY * HZN + NW - 1) / NW;   // rows per wavefront
+            double v0[NR], v1[NR];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int row = wv + j * NW;
+                if (row < HY * HZN) {
+                    const int hy = row % HY, hz = row / HY;
+                    const int gy = wrap(y0 - 1 + hy, ny), gz = wrap(z0 - HZ + hz, nz);
+                    const double *fr = f + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz);
+                    v0[j] = fr[gx0];
+                    v1[j] = fr[gx1];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int row = wv + j * NW;
+                if (row < HY * HZN) {
+                    lds[row * HX + lane] = v0[j];
+                    if (lane < 2) lds[row * HX + 64 + lane] = v1[j];
+                }
+            }
+        } else {
+            // NK halo points per thread
+            constexpr int NK = (NH + TPB - 1) / TPB;
+            double v[NK];
+#pragma unroll
+            for (int j = 0; j < NK; ++j) {
+                const int k = (int)threadIdx.x + j * TPB;
+                if (k < NH) {
+                    const int hx = k % HX, hy = (k / HX) % HY, hz = k / (HX * HY);
+                    const int gx = wrap(x0 - 1 + hx, nx), gy = wrap(y0 - 1 + hy, ny),
+                              gz = wrap(z0 - HZ + hz, nz);
+                    v[j] = f[(int64_t)gx + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz)];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NK; ++j) {
+                const int k = (int)threadIdx.x + j * TPB;
+                if (k < NH) lds[k] = v[j];
+            }
         }
     }
     __device__ void grad(const double *lds, double &gx, double &gy, double &gz) const {
