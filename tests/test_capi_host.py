@@ -36,10 +36,20 @@ def test_header_and_library_export_the_same_functions():
         assert hasattr(L, n), n
 
 
+# heavy pseudo-components: PR's alpha branch for omega > 0.49, and the
+# split itself (omega = 0.49 takes the first branch on both sides)
+HEAVY = [C.TABLE_I["C1"], C.Component("h049", 600.0, 20.0, 0.49, 180.0),
+         C.Component("h0491", 610.0, 19.0, 0.4901, 185.0),
+         C.Component("h06", 650.0, 17.0, 0.6, 220.0),
+         C.Component("h08", 720.0, 14.0, 0.8, 300.0),
+         C.Component("h10", 800.0, 12.0, 1.0, 400.0)]
+
+
 @pytest.mark.parametrize("comps,T,kij_seed", [
     (C.DROPLET_3, 250.0, None),
     (C.N_ALKANES, 325.0, 4),
     ([C.TABLE_I["C1"]], 177.24, None),
+    (HEAVY, 450.0, 7),
 ])
 @pytest.mark.parametrize("eos", ["PR", "SRK", "vdW"])
 def test_lattice_constants_match_oracle_units(comps, T, kij_seed, eos):

@@ -315,6 +315,20 @@ def test_maxwell_equal_area(eos):
     assert abs(area / (ps * (vV - vL)) - 1) < 1e-9
 
 
+def test_pr_heavy_alpha_branch_reproduces_the_acentric_factor():
+    """PR's second alpha branch (omega > 0.49, Section II.C) was fitted to
+    heavy components' vapour pressures: through the Maxwell construction at
+    Tr = 0.7 it returns the acentric factor's definition to 1e-4 for omega
+    in 0.5 ... 1.2.  Checked to 1e-3: a dropped cubic term, a flipped sign
+    or a coefficient taken from the first branch moves it by 0.003 to 0.28."""
+    from inputs.components import Component
+    for w in (0.6, 0.8, 1.0):
+        c = Component("x", 600.0, 20.0, w, 200.0)
+        mix = th.si_mixture([c], 0.7 * c.Tc, eos="PR")
+        ps, _, _ = th.maxwell(mix)
+        assert abs(-np.log10(ps / (c.pc * th.BAR)) - 1.0 - w) < 1e-3
+
+
 @pytest.mark.parametrize("eos", ["PR", "SRK"])
 def test_alpha_reproduces_the_acentric_factor(eos):
     """Both alpha correlations were fitted so that the EOS returns the
