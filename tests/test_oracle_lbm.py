@@ -261,6 +261,44 @@ def test_d3q19_reduces_to_d2q9_on_a_one_dimensional_field(oracle_lib):
     assert np.max(np.abs(ra - rb)) / np.max(np.abs(ra)) < 1e-12
 
 
+def _drop3d(n=10, seed=7):
+    """Two components, an off-centre spherical drop (no symmetry of the
+    cube maps it to itself) with seeded noise, [N][nz][ny][nx]."""
+    rhoL = np.array([1.428, 3.167])
+    rhoV = np.array([0.837, 0.0943])
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    d = np.sqrt((x - 4.3) ** 2 + (y - 5.6) ** 2 + (z - 3.2) ** 2)
+    prof = 0.5 * (1.0 - np.tanh((d - 3.0) / 2.0))
+    f = rhoV[:, None, None, None] + (rhoL - rhoV)[:, None, None, None] * prof[None]
+    return Fi.add_noise(f, 1e-3, seed)
+
+
+def test_d3q19_commutes_with_the_cube_symmetries(oracle_lib):
+    """D3Q19 (velocity set, weights, stencils, forcing) is invariant under
+    the symmetries of the cube, so on a genuinely three-dimensional field
+    with none of them, stepping a relabelled field equals relabelling the
+    stepped one: a cyclic permutation of the axes and a reflection of each
+    axis, after 30 steps.  One wrong lattice vector or weight among the 18
+    moving directions breaks one of these."""
+    mix, _ = _droplet_setup(N=2)
+    f = _drop3d()
+    n = f.shape[-1]
+
+    def run(field):
+        sim = lbm.OracleLBM(mix, 1, (n, n, n), np.ascontiguousarray(field))
+        sim.run(30)
+        assert sim.status == 0
+        return sim.rho()
+
+    base = run(f)
+    assert np.max(np.abs(base - f)) > 1e-3                   # the field did evolve
+    cyc = lambda a: np.transpose(a, (0, 2, 3, 1))          # relabel (z, y, x) -> (y, x, z)
+    np.testing.assert_allclose(run(cyc(f)), cyc(base), rtol=1e-12, atol=0)
+    for ax in (1, 2, 3):                                      # r -> -r along one axis
+        refl = lambda a, ax=ax: np.roll(np.flip(a, axis=ax), 1, axis=ax)
+        np.testing.assert_allclose(run(refl(f)), refl(base), rtol=1e-12, atol=0)
+
+
 def test_d3q19_flat_interface_relaxes_to_maxwell(oracle_lib):
     """Table II case 1 on a 128 x 1 x 1 D3Q19 slab: the bulk densities reach
     the Maxwell coexistence densities (even windows) with u at round-off."""
