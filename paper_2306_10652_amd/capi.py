@@ -3,8 +3,9 @@
 Argument marshalling only: every step of the method runs in the HIP
 kernels.  The functions keep the C names; ``Mixture`` and ``Simulation``
 are small owners of the opaque handles.  PyTorch is used for device memory
-(borrowed ``dev_buf``) and streams.  Importing this module on a machine
-without the built library raises; there is no CPU fallback.
+(borrowed ``dev_buf``) and streams.  The first call into the library on a
+machine without the built ``libfuglbm.so`` raises ImportError; there is no
+CPU fallback.
 """
 import ctypes
 import os
@@ -117,7 +118,8 @@ def check(status):
 def _dp(a):
     if a is None:
         return None
-    assert a.dtype == np.float64 and a.flags.c_contiguous
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous float64 array, got %s" % a.dtype)
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
