@@ -155,7 +155,7 @@ class Server:
                     try:
                         unit[0]["sim"].step_n(self.chunk, st)
                     except capi.FuglbmError:
-                        pass
+                        pass    # sticky: the residual read below retires it alone
             still = []
             for s in active:
                 req = s["req"]
