@@ -349,7 +349,7 @@ def main():
         print(json.dumps(dict(calib_copy_bytes=n * 4, launches=5)))
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported "
+        print("bench.py measures one GPU; --gpus %d is not supported "
               "(multi-GPU sharding is design-only)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
