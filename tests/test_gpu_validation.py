@@ -14,7 +14,9 @@ thermodynamics (what the paper validates in Section III):
 * ternary C1/C2/C3 flat interfaces on the flash tie lines (Section III.C);
 * three-component three-phase flat interfaces against the three-phase
   flash (Section III.D, Table VI);
-* iso-fugacity across a curved interface (Tables IX-X): f_i^L / f_i^V -> 1.
+* iso-fugacity across a curved interface (Tables IX-X): f_i^L / f_i^V -> 1;
+* D3Q19 against D2Q9 (the paper is 2-D only): a pure C1 drop obeys Young-
+  Laplace with slope 2 sigma in 3-D and sigma in 2-D, with the same sigma.
 
 Bulk states are averages over windows of even width: the central-difference
 gradient of the method cannot see a period-2 (odd-even) component of psi,
@@ -569,3 +571,83 @@ def test_ten_component_spinodal_iso_fugacity_tables_ix_x(case, T):
     # both phases present: molar density ratio of the windows near the flash's
     assert abs((liq.sum() / vap.sum()) / flash_ratio - 1) < 0.05
     assert np.max(np.abs(ratio - 1)) < 0.02
+
+
+def _drop_dp(sim, om, n, D):
+    """Equimolar radius and EOS pressure jump of a drop: 4-site windows
+    (even width) at the periodic centre of mass and at the point farthest
+    from it."""
+    rt = sim.read_moments(velocity=False)["rho"] / om.M[:, None, None, None]
+    tot = rt.sum(axis=0)                                    # [nz][ny][nx]
+    k = np.exp(2j * np.pi * np.arange(n) / n)
+
+    def centre(axes):
+        return int(np.floor(np.angle(np.sum(tot.sum(axis=axes) * k)) * n / (2 * np.pi))) % n
+
+    if D == 2:
+        c = (0, centre((0, 1)), centre((0, 2)))
+    else:
+        c = (centre((1, 2)), centre((0, 2)), centre((0, 1)))
+    w = np.arange(-1, 3)
+
+    def window(off):
+        idx = [(w + c[a] + off) % n if (D == 3 or a > 0) else np.array([0]) for a in range(3)]
+        return rt[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]].mean(axis=(1, 2, 3))
+
+    cin, cout = window(0), window(n // 2)
+    t_in, t_out = cin.sum(), cout.sum()
+    excess = np.sum(tot - t_out) / (t_in - t_out)           # drop volume
+    Re = np.sqrt(excess / np.pi) if D == 2 else (3 * excess / (4 * np.pi)) ** (1 / 3)
+    return Re, om.pr.pressure_rho(cin) - om.pr.pressure_rho(cout)
+
+
+def test_young_laplace_3d_slope_is_twice_the_2d_slope():
+    """A pure C1 drop (Table II case 1 coexistence densities, tanh profile
+    of width 4) at equilibrium: in 2-D (D2Q9, 128^2, R = 20 ... 44)
+    Delta p = sigma / R_e, in 3-D (D3Q19, 96^3, R = 24 ... 36) Delta p =
+    2 sigma / R_e.  The flat interface is one-dimensional, where D3Q19 and
+    D2Q9 coincide, so sigma is the same: Delta p is linear in 1 / R_e in
+    both (R^2 > 0.999, intercept under 3 % of the largest Delta p), and
+    the 3-D Delta p R_e is twice the 2-D one within 2 %.  (Smaller drops
+    shrink or evaporate in the closed box before they settle; an R = 20
+    drop in 3-D ends at R_e = 16 with Delta p R_e 1.5 % low.)"""
+    from oracle.lbm import oracle_mixture
+    capi = _capi()
+    comps, T, _ = C.table_ii_components(1)
+    st = W.states()["vle1"]
+    rL, rV = np.array(st["rho_L"]), np.array(st["rho_V"])
+    om = oracle_mixture(comps, T)
+    mix = capi.Mixture.from_components(comps, T)
+    slope = {}
+    for D, n, radii in ((2, 128, (20, 28, 36, 44)), (3, 96, (24, 28, 32, 36))):
+        ax = np.arange(n) - (n / 2 - 0.5)
+        if D == 2:
+            y, x = np.meshgrid(ax, ax, indexing="ij")
+            d = np.sqrt(x * x + y * y)[None]
+        else:
+            z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+            d = np.sqrt(x * x + y * y + z * z)
+        inv_R, dp = [], []
+        for R in radii:
+            prof = 0.5 * (1.0 - np.tanh((d - R) / 2.0))
+            rho = rV[:, None, None, None] + (rL - rV)[:, None, None, None] * prof[None]
+            shape = (n, n) if D == 2 else (n, n, n)
+            sim = capi.Simulation(mix, 0 if D == 2 else 1, 0, shape, rho)
+            sim.step_n(40000)
+            assert sim.diagnostics()["rc"] == 0
+            Re, p = _drop_dp(sim, om, n, D)
+            sim.close()
+            report("young_laplace_%dd" % D, R=R, Re=Re, dp=p, dpRe=p * Re)
+            inv_R.append(1.0 / Re)
+            dp.append(p)
+        inv_R, dp = np.array(inv_R), np.array(dp)
+        A = np.vstack([inv_R, np.ones_like(inv_R)]).T
+        (s_, c0), *_ = np.linalg.lstsq(A, dp, rcond=None)
+        fit = A @ np.array([s_, c0])
+        r2 = 1 - np.sum((dp - fit) ** 2) / np.sum((dp - dp.mean()) ** 2)
+        report("young_laplace_%dd_fit" % D, slope=s_, intercept=c0, r2=r2)
+        assert r2 > 0.999 and abs(c0) < 0.03 * dp.max()
+        slope[D] = float(np.mean(dp / inv_R))          # Delta p R_e
+    mix.close()
+    report("young_laplace_3d_over_2d", ratio=slope[3] / slope[2])
+    assert abs(slope[3] / (2 * slope[2]) - 1) < 0.02
