@@ -651,3 +651,35 @@ def test_young_laplace_3d_slope_is_twice_the_2d_slope():
     mix.close()
     report("young_laplace_3d_over_2d", ratio=slope[3] / slope[2])
     assert abs(slope[3] / (2 * slope[2]) - 1) < 0.02
+
+
+def test_d3q19_drop_fp32_storage_at_equilibrium():
+    """FP32 storage in 3-D, stated at equilibrium: the R = 28 pure C1 drop
+    of the Young-Laplace check (96^3, 4 10^4 steps) run in both
+    precisions; the bulk densities inside and outside and Delta p R_e agree
+    within the FP32-storage bar of 1e-4 relative."""
+    from oracle.lbm import oracle_mixture
+    capi = _capi()
+    comps, T, _ = C.table_ii_components(1)
+    st = W.states()["vle1"]
+    rL, rV = np.array(st["rho_L"]), np.array(st["rho_V"])
+    om = oracle_mixture(comps, T)
+    mix = capi.Mixture.from_components(comps, T)
+    n = 96
+    ax = np.arange(n) - (n / 2 - 0.5)
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    prof = 0.5 * (1.0 - np.tanh((np.sqrt(x * x + y * y + z * z) - 28.0) / 2.0))
+    rho = rV[:, None, None, None] + (rL - rV)[:, None, None, None] * prof[None]
+    got = {}
+    for prec in (0, 1):
+        sim = capi.Simulation(mix, 1, prec, (n, n, n), rho)
+        sim.step_n(40000)
+        assert sim.diagnostics()["rc"] == 0
+        r = sim.read_moments(velocity=False)["rho"][0]
+        Re, dp = _drop_dp(sim, om, n, 3)
+        got[prec] = (r[n // 2, n // 2, n // 2], r[0, 0, 0], dp * Re)
+        sim.close()
+    mix.close()
+    rel = [abs(a / b - 1) for a, b in zip(got[1], got[0])]
+    report("d3q19_drop_fp32", rho_in=rel[0], rho_out=rel[1], dpRe=rel[2])
+    assert max(rel) <= 1e-4
