@@ -188,10 +188,12 @@ def time_vs_n_leg(steps=2000):
                 us_per_step_fp32_storage=[round(u, 2) for u in us32])
 
 
-def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=None):
+def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=None,
+                max_n2d=256, max_n3d=64):
     """Continuous batching: Poisson arrivals of requests from the stored pool
-    (2-10 components; D2Q9 up to 256^2, D3Q19 up to 64^3 here so the leg
-    stays within a minute), FP32 storage, run to residual tol.  The arrival
+    (2-10 components; D2Q9 up to 256^2, D3Q19 up to 64^3 by default so the
+    leg stays within a minute; the `serving_full` leg keeps the pool's sizes,
+    up to 512^2 and 128^3), FP32 storage, run to residual tol.  The arrival
     rate offers `load` x the measured batched throughput, using the mean work
     of calibration requests served alone."""
     import torch
@@ -199,7 +201,7 @@ def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=No
     from inputs import fields as Fi
     S = Fi.load_phase_states()["serving_pool"]
     calib = serve.pool_requests(S, 4, rate_hz=1e6, tol=tol, max_steps=max_steps,
-                                max_n2d=256, max_n3d=64)
+                                max_n2d=max_n2d, max_n3d=max_n3d)
     work = []
     for r in calib:
         r.arrival = 0.0
@@ -209,14 +211,22 @@ def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=No
     cap = capacity_csu_s or 2.0e10
     rate = load * cap / mean_work
     reqs = serve.pool_requests(S, count, rate_hz=rate, tol=tol, max_steps=max_steps,
-                               max_n2d=256, max_n3d=64, seed=55)
+                               max_n2d=max_n2d, max_n3d=max_n3d, seed=55)
     srv = serve.Server(64 << 30, chunk=200)
     t0 = time.perf_counter()
-    done = srv.run(reqs)
+    last = [0.0]
+
+    def progress(t, active, waiting, done):
+        if t - last[0] >= 20.0:
+            last[0] = t
+            print("serving: %.0f s, %d active, %d waiting, %d done" % (t, active, waiting, done),
+                  file=sys.stderr, flush=True)
+    done = srv.run(reqs, progress=progress)
     wall = time.perf_counter() - t0
     st = serve.latency_stats(done)
     csu = sum(r.csu() for r in done if r.status == 0)
-    st.update(requests=count, offered_load=load, arrival_rate_hz=round(rate, 3),
+    st.update(requests=count, max_n2d=max_n2d, max_n3d=max_n3d, offered_load=load,
+              arrival_rate_hz=round(rate, 3),
               hbm_budget_gb=64, tol=tol, max_steps=max_steps, wall_s=round(wall, 3),
               throughput=dict(value=round(csu / wall, 1), unit="CSU/s"),
               failed=int(sum(r.status != 0 for r in done)))
@@ -325,7 +335,8 @@ def main():
                     help="skip the sweep, time-vs-N and serving legs")
     ap.add_argument("--legs", default="sweep,time_vs_n,serving,d3q19",
                     help="comma-separated extra legs to run (sweep, time_vs_n, serving, "
-                         "d3q19)")
+                         "d3q19; serving_full, the serving stream at the pool's own sizes, "
+                         "runs only when named)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
     ap.add_argument("--rows", type=int, default=0,
@@ -398,6 +409,9 @@ def main():
         out["serving"] = serving_leg(capacity_csu_s=cap)
     if "d3q19" in legs:
         out["d3q19"] = d3q19_leg()
+    if "serving_full" in legs:
+        cap = out["batched_sweep"]["fp32_batched"]["value"] if "batched_sweep" in out else None
+        out["serving_full"] = serving_leg(capacity_csu_s=cap, max_n2d=None, max_n3d=None)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -94,9 +94,10 @@ class Server:
         self.used -= req.nbytes()
         self.done.append(req)
 
-    def run(self, requests, clock=time.perf_counter):
+    def run(self, requests, clock=time.perf_counter, progress=None):
         """Serve `requests` (their `arrival` offsets are honoured in wall
-        clock) until all are finished.  Returns the finished requests."""
+        clock) until all are finished.  Returns the finished requests.
+        `progress(t, active, waiting, done)` is called after every tick."""
         pending = [(r.arrival, r.rid, r) for r in requests]
         heapq.heapify(pending)
         waiting = []          # arrived, not admitted (FIFO)
@@ -172,6 +173,8 @@ class Server:
                 else:
                     still.append(s)
             active = still
+            if progress is not None:
+                progress(clock() - t0, len(active), len(waiting), len(self.done))
         return self.done
 
 
