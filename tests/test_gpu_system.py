@@ -111,15 +111,19 @@ def test_fused_and_generic_kernels_agree():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_every_destination_written_nan_canary(precision):
+@pytest.mark.parametrize("lattice,shape", [(0, (67, 33)), (1, (70, 6, 5))])
+def test_every_destination_written_nan_canary(lattice, shape, precision):
     """Fill the destination buffer with NaN, take one step: every population
-    of the new state must be finite (push streaming writes each slot once)."""
+    of the new state must be finite (push streaming writes each slot once).
+    D2Q9 on the fused kernel; D3Q19 on a grid whose second 64-wide
+    collision tile holds 6 columns."""
     import torch
-    wl = W.random_droplet(4, (67, 33), seed=4)
+    wl = W.random_droplet(4, shape, seed=4, lattice=lattice)
     sim = make(wl, precision)
-    Q, ns = 9, 67 * 33
+    Q, ns = (9, 67 * 33) if lattice == 0 else (19, 70 * 6 * 5)
     # FP32 storage: FP64 rest populations, then FP32 moving ones, arrays
-    # 64 elements apart beyond the grid; FP64 rows of 67 columns are unpadded
+    # 64 elements apart beyond the grid; FP64 rows under 256 columns are
+    # unpadded
     pop_bytes = 4 * (ns + 64) * (8 + (Q - 1) * 4) if precision else 4 * Q * ns * 8
     pop_bytes = (pop_bytes + 255) // 256 * 256
     base = (sim._buf.data_ptr() + 255) & ~255
@@ -176,6 +180,21 @@ def test_sticky_error_and_isolation_in_batch():
     rc = capi.fuglbm_step_many([a, b], 10)
     assert rc == 5                      # a skipped, b advanced
     assert np.array_equal(b.read_populations(), ref)
+
+
+def test_sticky_error_d3q19():
+    """A non-finite population on the multi-pass D3Q19 path sets the sticky
+    status: the next diagnostics report it, later steps are refused."""
+    capi = _capi()
+    wl = W.random_droplet(3, (20, 18, 16), seed=5, lattice=1)
+    sim = make(wl, capi=capi)
+    sim.poke(1, 0, 20 * 18 * 8 + 20 * 9 + 10, float("nan"))
+    sim.step_n(3)
+    d = sim.diagnostics()
+    assert d["rc"] == 5 and d["status"] & 1
+    with pytest.raises(capi.FuglbmError) as e:
+        sim.step_n(1)
+    assert e.value.status == 5
 
 
 @pytest.mark.parametrize("precision", [0, 1])
