@@ -137,6 +137,23 @@ def test_every_destination_written_nan_canary(lattice, shape, precision):
     assert np.all(np.isfinite(g))
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_checkpoint_resume_bitwise_d3q19(precision):
+    """D3Q19, both precisions: 60 steps, read the populations out, write
+    them into a fresh simulation, 60 more steps == 120 steps straight."""
+    wl = W.random_droplet(3, (70, 6, 5), seed=8, lattice=1)
+    a = make(wl, precision)
+    a.step_n(120)
+    ref = a.read_populations()
+    b = make(wl, precision)
+    b.step_n(60)
+    ck = b.read_populations()
+    c = make(wl, precision)
+    c.write_populations(ck, 60)
+    c.step_n(60)
+    assert np.array_equal(c.read_populations(), ref)
+
+
 def test_checkpoint_resume_bitwise():
     wl = W.droplet64()
     a = make(wl)
