@@ -5,6 +5,7 @@
  * One step, for every lattice site r and component i (paper Section II):
  *   rho_i = sum_a g_{a,i};  rt_i = rho_i / M_i                (molar density)
  *   ln f_i from the Peng-Robinson EOS, Eq. (9)-(12), local in rt_1..rt_N
+ *           (SRK or van der Waals in its place: fuglbm_mixture_desc.eos)
  *   psi_i = RT ln f_i - sqrt(kappa_i) lap(sum_j sqrt(kappa_j) rt_j)
  *           (Eq. (3)-(5) with the rank-one kappa_ij of Eq. (4), kappa_i of Eq. (6))
  *   F_i = -rt_i grad(psi_i);  u = (sum_i sum_a e_a g_{a,i} + F/2) / rho
@@ -181,7 +182,7 @@ fuglbm_status fuglbm_diagnostics(fuglbm_sim *sim, fuglbm_diag *diag);
 fuglbm_status fuglbm_read_populations(fuglbm_sim *sim, double *g_out);
 fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int64_t step);
 
-/* Launch tuning: kernel 0 = automatic, 1 = three-pass generic kernels,
+/* Launch tuning: kernel 0 = automatic, 1 = four-pass generic kernels,
  * 2 = fused one-pass D2Q9 kernel (register ring), 3 = fused one-pass D2Q9
  * kernel with store wavefronts (ncomp <= 10; bit-identical results);
  * rows = output rows per fused work item (>= 1, fixed), or 0 = autotuned:
