@@ -1,6 +1,6 @@
-"""The benchmark's command-line contract, on the CPU (no GPU is touched):
-more than one GPU is refused with a message, and the stored HBM counter
-summary was taken on the fused kernels as they are (their source hash)."""
+"""The benchmark's contract, on the CPU (no GPU is touched): more than one
+GPU is refused with a message, the stored HBM counter summary was taken on
+the fused kernels as they are (their source hash), and the oracle leg runs."""
 import json
 import os
 import subprocess
@@ -25,3 +25,15 @@ def test_counter_summary_matches_the_kernel_sources():
     assert pm["kernel_sha256_16"] == bench.kernel_hash()
     assert pm["hbm_bytes_per_launch"] > 0
 
+
+
+def test_cpu_baseline_leg_on_a_small_field():
+    """The oracle leg of the benchmark (whole steps with every OpenMP thread,
+    then one step on one thread) on a 64^2 field of the same mixture: the
+    fields the bench line reports are there and positive."""
+    sys.path.insert(0, ROOT)
+    import bench
+    r = bench.cpu_baseline(64, budget_s=0.2)
+    assert r["kind"] == "oracle" and r["unit"] == "CSU/s"
+    assert r["value"] > 0 and r["one_thread"]["value"] > 0
+    assert r["cores"] >= 1 and "64x64" in r["sample"]
