@@ -7,5 +7,9 @@ call or load anything in this package.  The GPU library
 
 * ``thermo``     Peng-Robinson EOS (Eq. 9-12), lattice units, flash, Maxwell.
 * ``lbm``        front of ``lbm_oracle.c``: the plain FP64 LBM step (Eq. 1-5).
-* ``analysis``   bulk-phase readouts used by validation tests.
+* ``write_phase_states``  the only writer of the stored phase states
+  (``inputs/phase_states.json``).
+
+The bulk-window, Laplace-pressure and iso-fugacity read-outs of the
+validation tests are written in those tests, over oracle thermodynamics.
 """

@@ -74,6 +74,8 @@ def lib():
         L.oracle_run.restype = ctypes.c_int
         L.oracle_fields.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         L.oracle_fields.restype = ctypes.c_int
+        L.oracle_diagnostics.argtypes = [pp, dp, dp, ctypes.c_long, dp, dp, dp, dp]
+        L.oracle_diagnostics.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -190,6 +192,20 @@ class OracleLBM:
 
     def rho(self):
         return self.fields()["rho"]
+
+    def diagnostics(self, g_prev=None, K=0):
+        """Mass per component, the populations' momentum, the force-corrected
+        momentum sum_r rho u and the residual against g_prev (a copy of
+        ``self.g`` taken K steps earlier), plus status bits."""
+        N = self.mix.N
+        mass = np.zeros(N)
+        mp = np.zeros(3)
+        mu = np.zeros(3)
+        res = ctypes.c_double()
+        gp = None if g_prev is None else np.ascontiguousarray(g_prev, dtype=np.float64)
+        st = lib().oracle_diagnostics(ctypes.byref(self.P), _dp(self.g), _dp(gp), int(K),
+                                      _dp(mass), _dp(mp), _dp(mu), ctypes.byref(res))
+        return dict(mass=mass, momentum_pop=mp, momentum=mu, residual=res.value, status=st)
 
     def populations(self):
         """Populations as [N][Q][sites] (for comparisons only)."""

@@ -407,6 +407,59 @@ int oracle_fields(const oracle_params *P, const double *g, double *rho, double *
     return status;
 }
 
+/* ---- diagnostics of a state (mass, momentum, residual, status) ---------- */
+/* For the state g (and, for the residual, the state g_prev taken K steps
+ * earlier), summed site by site in site order:
+ *   mass[i]     = sum_r rho_i(r)                       (per-component mass;
+ *                 conserved by Eq. (1a)-(1c): sum_a F_a = 0 and
+ *                 sum_a (geq - g) = 0, and streaming only moves populations);
+ *   mom_pop[d]  = sum_r sum_i sum_a e_a g              (the populations' own
+ *                 momentum);
+ *   mom_u[d]    = sum_r (sum_i sum_a e_a g + F_d / 2)  (= sum_r rho u, the
+ *                 force-corrected momentum of the common velocity u);
+ *   residual    = max_i sum_r |rho_i(t) - rho_i(t-K)| / (K sum_r rho_i(t)),
+ *                 0 when g_prev is NULL or K <= 0;
+ * and returns the status bits of the state's fields (1 non-finite ln f_i,
+ * 2 outside the EOS domain, 4 some rt_i <= 0).                              */
+int oracle_diagnostics(const oracle_params *P, const double *g, const double *g_prev, long K,
+                       double *mass, double *mom_pop, double *mom_u, double *residual) {
+    const int N = P->N;
+    long ns = nsites(P);
+    fields f;
+    fields_alloc(P, &f);
+    int status = compute_fields(P, g, &f);
+    for (int d = 0; d < 3; ++d) {
+        mom_pop[d] = 0.0;
+        mom_u[d] = 0.0;
+    }
+    for (int i = 0; i < N; ++i) mass[i] = 0.0;
+    for (long s = 0; s < ns; ++s) {
+        for (int i = 0; i < N; ++i) mass[i] += f.rho[(size_t)i * ns + s];
+        for (int d = 0; d < 3; ++d) {
+            double Fs = 0.0;
+            for (int i = 0; i < N; ++i) Fs += f.F[((size_t)i * 3 + d) * ns + s];
+            mom_pop[d] += f.j[(size_t)d * ns + s];
+            mom_u[d] += f.j[(size_t)d * ns + s] + 0.5 * Fs;
+        }
+    }
+    *residual = 0.0;
+    if (g_prev && K > 0) {
+        fields fp;
+        fields_alloc(P, &fp);
+        compute_fields(P, g_prev, &fp);
+        for (int i = 0; i < N; ++i) {
+            double num = 0.0;
+            for (long s = 0; s < ns; ++s)
+                num += fabs(f.rho[(size_t)i * ns + s] - fp.rho[(size_t)i * ns + s]);
+            double r = num / ((double)K * mass[i]);
+            if (r > *residual) *residual = r;
+        }
+        fields_free(&fp);
+    }
+    fields_free(&f);
+    return status;
+}
+
 /* Thread count of the OpenMP loops (for timing the oracle at 1 thread and
  * at all cores); returns the count in effect before the call. */
 int oracle_set_threads(int n) {
