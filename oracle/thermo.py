@@ -21,6 +21,10 @@ Contents, each following the paper's Section II.C unless noted:
                                construction.  The paper uses a flash but does not
                                print its algorithm; these are written from the
                                thermodynamics, not from any listing.
+* ``stability``             -- Michelsen's tangent-plane (TPD) stability test
+                               of a feed at (T, p): stationary points of the
+                               tangent-plane distance by successive substitution
+                               from vapour- and liquid-like Wilson trials.
 * ``flash3``                -- the three-phase flash of the three-phase case
                                (Section III.D): multiphase Rachford-Rice and
                                successive substitution, written from the same
@@ -248,6 +252,75 @@ def rachford_rice(z, K, tol=1e-15, maxit=200):
             break
         beta = nb
     return beta
+
+
+def min_gibbs_phase(mix, x, p):
+    """The cubic root of a single phase of composition x at (T, p) with the
+    lowest molar Gibbs energy, i.e. the smallest sum_i x_i ln phi_i (the
+    stable root when the cubic has three): returns (Z, ln phi)."""
+    roots, _, _ = mix.z_roots(x, p)
+    if not roots:
+        raise ValueError("no admissible cubic root")
+    best = None
+    for Z in (roots[0], roots[-1]):
+        lp = mix.ln_phi(x, Z, p)
+        g = float(np.asarray(x) @ lp)
+        if best is None or g < best[0]:
+            best = (g, Z, lp)
+    return best[1], best[2]
+
+
+@dataclass
+class StabilityResult:
+    stable: bool          # no trial phase lowers the Gibbs energy
+    tm_min: float         # smallest tangent-plane distance at a non-trivial stationary point
+    w: np.ndarray         # composition of that trial phase (z if only trivial ones)
+    trials: list          # (tm, w, trivial) of the vapour- and liquid-like searches
+
+
+def stability(mix, z, p, tol=1e-12, maxit=5000, tm_tol=1e-10):
+    """Michelsen's tangent-plane stability test of a feed z at (T, p).
+
+    With d_i = ln z_i + ln phi_i(z) (the feed's stable root), the modified
+    tangent-plane distance of a trial phase of mole numbers W is
+        tm(W) = 1 + sum_i W_i (ln W_i + ln phi_i(w) - d_i - 1),  w = W / sum W,
+    whose stationary points satisfy ln W_i = d_i - ln phi_i(w); there
+    tm = 1 - sum W.  Two searches by successive substitution on that
+    condition start from the Wilson vapour-like (W = z K) and liquid-like
+    (W = z / K) trials.  The feed is unstable (splits into two phases) when
+    a search ends at a non-trivial stationary point (w != z) with tm < 0.
+    """
+    z = np.asarray(z, dtype=np.float64)
+    z = z / z.sum()
+    _, lpz = min_gibbs_phase(mix, z, p)
+    d = np.log(z) + lpz
+    K = wilson_K(mix, p)
+    trials = []
+    for W0 in (z * K, z / K):
+        lnW = np.log(W0)
+        trivial = False
+        for _ in range(maxit):
+            W = np.exp(lnW)
+            w = W / W.sum()
+            _, lpw = min_gibbs_phase(mix, w, p)
+            new = d - lpw
+            step = np.max(np.abs(new - lnW))
+            lnW = new
+            if np.max(np.abs(w - z)) < 1e-7:
+                trivial = True
+                break
+            if step < tol:
+                break
+        W = np.exp(lnW)
+        w = W / W.sum()
+        trivial = trivial or np.max(np.abs(w - z)) < 1e-7
+        trials.append((1.0 - float(W.sum()), w, trivial))
+    nontriv = [t for t in trials if not t[2]]
+    if nontriv:
+        tm, w, _ = min(nontriv, key=lambda t: t[0])
+    else:
+        tm, w = 0.0, z
+    return StabilityResult(bool(tm >= -tm_tol), float(tm), w, trials)
 
 
 @dataclass

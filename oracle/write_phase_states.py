@@ -30,7 +30,8 @@ BAR = th.BAR
 
 
 def two_phase_state(comps, T, p_bar, z, kij=None):
-    """Flash at (T, p, z) in lattice units; returns dict or None if one phase."""
+    """Stability test and flash at (T, p, z) in lattice units; returns dict
+    or None if one phase."""
     om = oracle_mixture(comps, T, kij)
     pr = om.pr
     p_lu = om.units.p(p_bar * BAR)
@@ -39,6 +40,11 @@ def two_phase_state(comps, T, p_bar, z, kij=None):
         return dict(p_lu=ps, p_bar=ps * om.units.p_scale / BAR, beta=None, S_V=0.5,
                     rho_V=list(om.M * rV), rho_L=list(om.M * rL),
                     x=[1.0], y=[1.0])
+    # Michelsen's stability test decides whether the feed splits; the flash
+    # then gives the phases (a flash that finds no split of an unstable
+    # feed, or a split of a stable one, rejects the draw)
+    if th.stability(pr, z, p_lu).stable:
+        return None
     r = th.flash(pr, z, p_lu)
     if not r.two_phase:
         return None

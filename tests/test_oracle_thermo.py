@@ -340,3 +340,90 @@ def test_alpha_reproduces_the_acentric_factor(eos):
         mix = th.si_mixture([c], 0.7 * c.Tc, eos=eos)
         ps, _, _ = th.maxwell(mix)
         assert abs(-np.log10(ps / (c.pc * th.BAR)) - 1.0 - w) < 0.02
+
+
+# ---------------------------------------------------------------------------
+# Michelsen's tangent-plane stability test (the flash's phase-split decision)
+# ---------------------------------------------------------------------------
+
+def _case_mixture(case):
+    from oracle.lbm import oracle_mixture
+    comps, T, p = C.table_ii_components(case)
+    om = oracle_mixture(comps, T)
+    return om, om.units.p(p * th.BAR), np.ones(len(comps)) / len(comps)
+
+
+@pytest.mark.parametrize("case", [2, 3, 4, 5, 6])
+def test_stability_table_iii_states_split(case):
+    """Table II cases 2-6 at their (T, p) and equimolar z are two-phase in
+    the paper (Table III): the feed is unstable, with the incipient phase
+    found by one of the two searches."""
+    om, p, z = _case_mixture(case)
+    r = th.stability(om.pr, z, p)
+    assert not r.stable and r.tm_min < -1e-3
+
+
+def test_stability_single_phase_states():
+    """Single-phase feeds are stable: Table II case 3's mixture above every
+    component's critical temperature, the same mixture at a pressure far
+    below its dew point, and a pure component anywhere off saturation."""
+    from oracle.lbm import oracle_mixture
+    comps, T, p = C.table_ii_components(3)
+    z = np.ones(3) / 3
+    hot = oracle_mixture(comps, 600.0)
+    assert th.stability(hot.pr, z, hot.units.p(p * th.BAR)).stable
+    om, _, _ = _case_mixture(3)
+    assert th.stability(om.pr, z, om.units.p(0.5 * th.BAR)).stable
+    pure = oracle_mixture(comps[:1], T)
+    for pb in (5.0, 30.0, 80.0):
+        assert th.stability(pure.pr, [1.0], pure.units.p(pb * th.BAR)).stable
+
+
+@pytest.mark.parametrize("case", [2, 3])
+def test_stability_changes_sign_at_the_tie_line_end(case):
+    """On the flash tie line at fixed (T, p): a feed just inside the two-phase
+    segment [x, y] is unstable, one just outside (beyond the liquid x) is
+    stable for the binary, and the liquid x itself sits on the boundary:
+    its vapour-like stationary point is the equilibrium vapour y with a
+    tangent-plane distance of zero."""
+    om, p, z = _case_mixture(case)
+    f = th.flash(om.pr, z, p)
+    assert f.two_phase
+    x, y = f.x, f.y
+    eps = 0.01
+    assert not th.stability(om.pr, x + eps * (y - x), p).stable
+    r = th.stability(om.pr, x, p)
+    tm_v, w_v, triv = r.trials[0]
+    assert not triv
+    assert abs(tm_v) < 1e-9
+    np.testing.assert_allclose(w_v, y, atol=1e-7)
+    if case == 2:                      # a binary: outside the segment is single-phase
+        assert th.stability(om.pr, x - eps * (y - x), p).stable
+
+
+def test_stored_two_phase_states_are_unstable_feeds():
+    """Every stored multi-component two-phase state (sweep and serving draws,
+    the Section III cases) is an unstable feed at its own (T, p, z): the
+    stability test gates the state writer, and gating changes none of the
+    stored draws."""
+    from oracle.lbm import oracle_mixture
+    from inputs import fields as Fi
+    S = Fi.load_phase_states()
+    comp = lambda lst: [C.Component(**{k: c[k] for k in C.Component._fields}) for c in lst]
+    checked = 0
+    for key in ("droplet3", "vle2", "vle3", "vle4", "vle5", "vle6", "spinodal10",
+                "ten_co2_325", "ten_co2_400"):
+        st = S[key]
+        cs = comp(st["components"])
+        om = oracle_mixture(cs, st["T"], np.array(st["kij"]) if "kij" in st else None)
+        assert not th.stability(om.pr, st["z"], st["p_lu"]).stable, key
+        checked += 1
+    for group, key in (("ternary_sweep", "instances"), ("serving_pool", "requests"),
+                       ("ternary_c1c2c3", "instances")):
+        cs_all = comp(S[group]["components"])
+        for q in S[group][key]:
+            cs = cs_all[:q["N"]] if "N" in q else cs_all
+            om = oracle_mixture(cs, q["T"])
+            assert not th.stability(om.pr, q["z"], om.units.p(q["p_bar_in"] * th.BAR)).stable
+            checked += 1
+    assert checked > 400
