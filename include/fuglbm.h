@@ -108,11 +108,17 @@ typedef struct {
     int32_t eos;                   /* fuglbm_eos; 0 (a zeroed descriptor) = PR */
 } fuglbm_mixture_desc;
 
-/* Diagnostics (FP64 sums in a fixed order: bitwise reproducible). */
+/* Diagnostics of the current state (paper Section II.A: Eq. (1a)-(1c)
+ * conserve every component's mass, since sum_a F_a = 0, sum_a (geq - g) = 0
+ * and streaming only moves populations).  FP64 sums in a fixed order over a
+ * fixed site assignment (no float atomics): bitwise reproducible for a given
+ * grid.  Unused momentum components (z in 2-D) are 0. */
 typedef struct {
     int64_t step;                  /* steps taken since init */
     double mass[FUGLBM_MAX_COMP];  /* sum_r rho_i */
-    double momentum[3];            /* sum_r sum_i sum_a e_a g_{a,i} (populations' own momentum) */
+    double momentum[3];            /* sum_r (sum_i sum_a e_a g_{a,i} + F/2) = sum_r rho u,
+                                      the force-corrected momentum, F = sum_i F_i */
+    double momentum_pop[3];        /* sum_r sum_i sum_a e_a g_{a,i} (populations' own) */
     double residual;               /* max_i sum_r |rho_i(t) - rho_i(t-K)| / (K sum_r rho_i(t)),
                                       K = steps since the previous diagnostics call
                                       (0 on the first call) */
@@ -173,7 +179,11 @@ fuglbm_status fuglbm_read_moments(fuglbm_sim *sim, double *rho_out, double *u_ou
                                   fuglbm_diag *diag);
 
 /* Synchronise and compute mass, momentum, residual and status (see
- * fuglbm_diag).  Keeps rho_i(t) as the snapshot for the next residual. */
+ * fuglbm_diag): one pass of the fields kernels over the current state, then
+ * wavefront (DPP) reductions into per-block partials and one fixed-order
+ * final sum per quantity.  Keeps rho_i(t) (FP64) as the snapshot for the
+ * next residual.  Returns ENONFINITE if a status bit is set (diag is still
+ * filled). */
 fuglbm_status fuglbm_diagnostics(fuglbm_sim *sim, fuglbm_diag *diag);
 
 /* Checkpoint / restore the raw populations, host [ncomp][Q][sites] FP64

@@ -58,12 +58,14 @@ class Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64),
                 ("mass", ctypes.c_double * FUGLBM_MAX_COMP),
                 ("momentum", ctypes.c_double * 3),
+                ("momentum_pop", ctypes.c_double * 3),
                 ("residual", ctypes.c_double),
                 ("status", ctypes.c_uint32)]
 
     def as_dict(self, ncomp):
         return dict(step=self.step, mass=np.array(self.mass[:ncomp]),
-                    momentum=np.array(self.momentum[:]), residual=self.residual,
+                    momentum=np.array(self.momentum[:]),
+                    momentum_pop=np.array(self.momentum_pop[:]), residual=self.residual,
                     status=self.status)
 
 
@@ -292,3 +294,4 @@ def fuglbm_step_many(sims, nsteps, stream=None):
 
 def step_many(sims, nsteps, stream=None):
     check(fuglbm_step_many(sims, nsteps, stream))
+

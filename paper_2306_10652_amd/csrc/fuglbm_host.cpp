@@ -164,7 +164,7 @@ static Carve carve(int N, int lat, bool fp32, int nx, int ny, int nz) {
     c.j = o; o += align256((size_t)D * ns * 8);
     c.u = o; o += align256((size_t)D * ns * 8);
     c.snap = o; o += align256((size_t)N * ns * 8);
-    c.part = o; o += align256((size_t)1024 * (2 * N + 3) * 8);
+    c.part = o; o += align256(((size_t)1024 + 1) * (N + 1) * DIAG_QUANT * 8);
     c.fsim = o; o += align256(sizeof(FusedSim));
     c.max_items = 0;
     if (lat == 0) {
@@ -764,8 +764,9 @@ fuglbm_status fuglbm_read_moments(fuglbm_sim *s, double *rho_out, double *u_out,
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
     hipStream_t st = s->last_stream;
     HIP_TRY(hipStreamSynchronize(st));
-    HIP_TRY(launch_fields(s->lattice, s->fp32, s->dc, s->ns, s->buf[s->parity], s->rho_f,
-                          s->psi_f, s->s_f, s->j_f, u_out ? s->u_f : nullptr, s->status, st));
+    HIP_TRY(launch_fields(s->lattice, s->fp32, s->dc, s->nx, s->ny, s->nz, s->buf[s->parity],
+                          s->rho_f, s->psi_f, s->s_f, s->j_f, u_out ? s->u_f : nullptr, s->status,
+                          st));
     HIP_TRY(hipStreamSynchronize(st));
     if (rho_out)
         HIP_TRY(hipMemcpy(rho_out, s->rho_f, (size_t)s->N * s->ns * 8, hipMemcpyDeviceToHost));
@@ -781,27 +782,35 @@ fuglbm_status fuglbm_read_moments(fuglbm_sim *s, double *rho_out, double *u_out,
     return FUGLBM_OK;
 }
 
+// Diagnostics: the fields pass (rho_i, j, force-corrected u of the current
+// state), then per-block partial sums and one fixed-order final sum per
+// quantity on the device; the host reads the (N + 1) x DIAG_QUANT totals.
 fuglbm_status fuglbm_diagnostics(fuglbm_sim *s, fuglbm_diag *diag) {
     if (!s || !diag) return fail(FUGLBM_EINVAL, "null argument");
     hipStream_t st = s->last_stream;
     const int nblk = diag_blocks(s->ns);
-    const int N = s->N, nq = 2 * N + 3;
-    HIP_TRY(launch_diag(s->lattice, s->fp32, s->dc, s->ns, s->buf[s->parity], s->snap, s->part,
-                        nblk, s->have_snap ? 1 : 0, st));
+    const int N = s->N;
+    double *fin = s->part + (size_t)1024 * (N + 1) * DIAG_QUANT;
+    HIP_TRY(launch_fields(s->lattice, s->fp32, s->dc, s->nx, s->ny, s->nz, s->buf[s->parity],
+                          s->rho_f, s->psi_f, s->s_f, s->j_f, s->u_f, s->status, st));
+    HIP_TRY(launch_diag(s->D, N, s->ns, s->rho_f, s->j_f, s->u_f, s->snap, s->part, nblk, fin,
+                        s->have_snap ? 1 : 0, st));
+    double tot[(FUGLBM_MAX_COMP + 1) * DIAG_QUANT];
+    HIP_TRY(hipMemcpyAsync(tot, fin, sizeof(double) * (N + 1) * DIAG_QUANT, hipMemcpyDeviceToHost,
+                           st));
     HIP_TRY(hipStreamSynchronize(st));
-    std::vector<double> part((size_t)nblk * nq);
-    HIP_TRY(hipMemcpy(part.data(), s->part, part.size() * 8, hipMemcpyDeviceToHost));
-    std::vector<double> tot(nq, 0.0);
-    for (int b = 0; b < nblk; ++b)
-        for (int q = 0; q < nq; ++q) tot[q] += part[(size_t)b * nq + q];
     std::memset(diag, 0, sizeof(*diag));
     diag->step = s->step;
-    for (int i = 0; i < N; ++i) diag->mass[i] = tot[i];
-    for (int d = 0; d < 3; ++d) diag->momentum[d] = tot[2 * N + d];
+    for (int i = 0; i < N; ++i) diag->mass[i] = tot[i * DIAG_QUANT];
+    for (int d = 0; d < s->D; ++d) {
+        diag->momentum_pop[d] = tot[N * DIAG_QUANT + d];
+        diag->momentum[d] = tot[N * DIAG_QUANT + 3 + d];
+    }
     double res = 0.0;
     const int64_t K = s->step - s->snap_step;
     if (s->have_snap && K > 0)
-        for (int i = 0; i < N; ++i) res = std::max(res, tot[N + i] / ((double)K * tot[i]));
+        for (int i = 0; i < N; ++i)
+            res = std::max(res, tot[i * DIAG_QUANT + 1] / ((double)K * tot[i * DIAG_QUANT]));
     diag->residual = res;
     s->have_snap = true;
     s->snap_step = s->step;

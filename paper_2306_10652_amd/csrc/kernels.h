@@ -29,11 +29,19 @@ hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int nc
                                int nz, const void *gs, void *gd, double *rho_f, double *psi_f,
                                double *s_f, double *j_f, double *u_f, uint32_t *status,
                                bool keep_old, hipStream_t st);
-hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
-                         double *rho_f, double *psi_f, double *s_f, double *j_f, double *u_f,
-                         uint32_t *status, hipStream_t st);
-hipError_t launch_diag(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
-                       double *snap, double *part, int nblk, int use_snap, hipStream_t st);
+// Macroscopic fields of a state: rho_i, RT ln f_i -> psi_i, s, j and (u_f
+// non-null) the force-corrected velocity.
+hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int nx, int ny, int nz,
+                         const void *g, double *rho_f, double *psi_f, double *s_f, double *j_f,
+                         double *u_f, uint32_t *status, hipStream_t st);
+// Diagnostic sums over the fields (rho_i, j, u): per-block partials in
+// part[(ncomp + 1) * nblk * DIAG_QUANT], final sums in out[(ncomp + 1) * DIAG_QUANT]:
+// out[i] = {mass_i, sum |rho_i - snap_i|, 0...} for i < ncomp (snap_i <- rho_i),
+// out[ncomp] = {sum j (3), sum rho u (3)}.
+constexpr int DIAG_QUANT = 6;
+hipError_t launch_diag(int dim, int ncomp, int64_t ns, const double *rho_f, const double *j_f,
+                       const double *u_f, double *snap, double *part, int nblk, double *out,
+                       int use_snap, hipStream_t st);
 int diag_blocks(int64_t ns);
 
 // Fused one-pass D2Q9 step over a table of work items (any mix of

@@ -160,32 +160,6 @@ __global__ __launch_bounds__(TPB) void k_interface(const SimConst *__restrict__ 
     for (int i = 0; i < N; ++i) psi_f[(int64_t)i * ns + s] -= c->sqk[i] * lap;
 }
 
-// Force-corrected common velocity u = (j + F/2) / rho at one site.
-template <class L>
-__device__ __forceinline__ void site_velocity(const SimConst *c, int64_t s, const int64_t *nb,
-                                              const double *rho_f, const double *psi_f,
-                                              const double *j_f, double &ux, double &uy,
-                                              double &uz, double &rhot) {
-    const int64_t ns = c->nsites;
-    const int N = c->N;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    rhot = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double *ps = psi_f + (int64_t)i * ns;
-        double gx, gy, gz;
-        lattice_grad<L>(nb, [&](int64_t t) { return ps[t]; }, gx, gy, gz);
-        const double r = rho_f[(int64_t)i * ns + s];
-        const double rt = r * c->invM[i];
-        Fx -= rt * gx;
-        Fy -= rt * gy;
-        Fz -= rt * gz;
-        rhot += r;
-    }
-    ux = (j_f[s] + 0.5 * Fx) / rhot;
-    uy = (j_f[ns + s] + 0.5 * Fy) / rhot;
-    uz = (L::D == 3) ? (j_f[2 * ns + s] + 0.5 * Fz) / rhot : 0.0;
-}
-
 // ---- LDS-tiled force, velocity and collision --------------------------------
 // A workgroup owns a tile of TX x TY x TZ sites (one thread per site) and
 // stages psi_i (and rho_i) over the tile plus a one-site halo in LDS, so
@@ -484,85 +458,105 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
     }
 }
 
-template <class L>
-__global__ __launch_bounds__(TPB) void k_velocity(const SimConst *__restrict__ c,
-                                                  const double *__restrict__ rho_f,
-                                                  const double *__restrict__ psi_f,
-                                                  const double *__restrict__ j_f,
-                                                  double *__restrict__ u_f) {
-    const int64_t ns = c->nsites;
-    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (s >= ns) return;
-    const int nx = c->nx, ny = c->ny, nz = c->nz;
-    const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((int64_t)nx * ny));
-    int64_t nb[L::Q];
-#pragma unroll
-    for (int a = 0; a < L::Q; ++a) nb[a] = nb_site<L>(x, y, z, a, nx, ny, nz);
-    double ux, uy, uz, rhot;
-    site_velocity<L>(c, s, nb, rho_f, psi_f, j_f, ux, uy, uz, rhot);
-    u_f[s] = ux;
-    u_f[ns + s] = uy;
-    if (L::D == 3) u_f[2 * ns + s] = uz;
+// Diagnostics from the macroscopic fields of the current state (rho_i,
+// j and the force-corrected u written by the fields pass): per-block
+// partial sums over a fixed site assignment, then one fixed-order final
+// sum per quantity.  Sums within a wavefront go through DPP lane moves in
+// a fixed pattern, the four wavefronts of a block are added in wavefront
+// order, and no float atomics are used, so the result is bitwise
+// reproducible for a given grid.
+//
+// Groups (blockIdx.y): y < N is component y: [0] sum_r rho_y,
+// [1] sum_r |rho_y - snap_y| (and snap_y <- rho_y); y == N is the
+// momentum: [0..3) sum_r j, [3..6) sum_r rho u.  part[y][b][6].
+constexpr int DIAG_Q = DIAG_QUANT;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
 }
 
-// Diagnostics: per-block partial sums over a fixed site assignment
-// (block b, thread t handle sites t + TPB*(b + nblk*k)), one pass over the
-// populations; the host adds the block partials in block order, so the
-// result is bitwise reproducible.
-// part[b][0..N) mass, [N..2N) sum |rho_i - snap_i|, [2N..2N+3) momentum.
-template <class L, typename ST>
-__global__ __launch_bounds__(TPB) void k_diag(const SimConst *__restrict__ c,
-                                              const void *__restrict__ g,
-                                              double *__restrict__ snap,
-                                              double *__restrict__ part, int use_snap) {
-    __shared__ double red[TPB];
-    const int64_t ns = c->nsites;
-    const int N = c->N, nx = c->nx;
-    const PopLayout<ST> P(N, L::Q, nx, (int64_t)c->ny * c->nz);
-    const int nq = 2 * N + 3;
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront (every lane active), the same
+// value on every lane: quad_perm [1,0,3,2] and [2,3,0,1] (quads),
+// row_half_mirror (8 lanes), row_mirror (16 lanes), then the four rows.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Block sum of DIAG_Q values per thread into out[DIAG_Q] (thread 0).
+__device__ __forceinline__ void block_sum(const double (&v)[DIAG_Q], double *out) {
+    __shared__ double ws[TPB / 64][DIAG_Q];
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < DIAG_Q; ++q) {
+        const double t = wave_sum(v[q]);
+        if ((threadIdx.x & 63) == 0) ws[wv][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < DIAG_Q) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < TPB / 64; ++w) t += ws[w][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_diag_part(int N, int64_t ns, const double *__restrict__ rho_f,
+                                                   const double *__restrict__ j_f,
+                                                   const double *__restrict__ u_f,
+                                                   double *__restrict__ snap,
+                                                   double *__restrict__ part, int use_snap) {
+    const int y = blockIdx.y;
     const int64_t stride = (int64_t)gridDim.x * TPB;
-    double mass[FUG_MAXC], res[FUG_MAXC], mom[3] = {0.0, 0.0, 0.0};
+    double v[DIAG_Q] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (y < N) {
+        const double *r = rho_f + (int64_t)y * ns;
+        double *sn = snap + (int64_t)y * ns;
+        for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < ns; s += stride) {
+            const double rv = r[s];
+            v[0] += rv;
+            if (use_snap) v[1] += fabs(rv - sn[s]);
+            sn[s] = rv;
+        }
+    } else {
+        for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < ns; s += stride) {
+            double rt = 0.0;
+            for (int i = 0; i < N; ++i) rt += rho_f[(int64_t)i * ns + s];
 #pragma unroll
-    for (int i = 0; i < FUG_MAXC; ++i) mass[i] = res[i] = 0.0;
-    for (int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x; s < ns; s += stride) {
-        const int64_t row = s / nx;
-        const int x = (int)(s - row * nx);
-#pragma unroll
-        for (int i = 0; i < FUG_MAXC; ++i) {
-            if (i < N) {
-                double r = 0.0;
-#pragma unroll
-                for (int a = 0; a < L::Q; ++a) {
-                    const double v = ld_pop<ST>(g, P, row, i, a, x);
-                    r += v;
-                    mom[0] += L::ex(a) * v;
-                    mom[1] += L::ey(a) * v;
-                    mom[2] += L::ez(a) * v;
-                }
-                mass[i] += r;
-                double *sp = snap + (int64_t)i * ns + s;
-                if (use_snap) res[i] += fabs(r - *sp);
-                *sp = r;
+            for (int d = 0; d < D; ++d) {
+                v[d] += j_f[(int64_t)d * ns + s];
+                v[3 + d] += rt * u_f[(int64_t)d * ns + s];
             }
         }
     }
-    for (int q = 0; q < nq; ++q) {
-        double v = 0.0;
+    block_sum(v, part + ((int64_t)y * gridDim.x + blockIdx.x) * DIAG_Q);
+}
+
+// Final sums: group y adds its nblk block partials, thread t taking blocks
+// t, t + TPB, ... in order; out[y][DIAG_Q].
+__global__ __launch_bounds__(TPB) void k_diag_final(const double *__restrict__ part, int nblk,
+                                                    double *__restrict__ out) {
+    const int y = blockIdx.x;
+    double v[DIAG_Q] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += TPB) {
+        const double *p = part + ((int64_t)y * nblk + b) * DIAG_Q;
 #pragma unroll
-        for (int i = 0; i < FUG_MAXC; ++i) {
-            if (i < N && q == i) v = mass[i];
-            if (i < N && q == N + i) v = res[i];
-        }
-        if (q >= 2 * N) v = mom[q - 2 * N];
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int w = TPB / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nq + q] = red[0];
-        __syncthreads();
+        for (int q = 0; q < DIAG_Q; ++q) v[q] += p[q];
     }
+    block_sum(v, out + (int64_t)y * DIAG_Q);
 }
 
 inline unsigned nblocks(int64_t ns) { return (unsigned)((ns + TPB - 1) / TPB); }
@@ -589,16 +583,18 @@ hipError_t step_generic_t(const SimConst *c, int ncomp, int64_t ns, int nx, int 
 }
 
 template <class L, typename ST>
-hipError_t fields_generic_t(const SimConst *c, int64_t ns, const void *g, double *rho_f,
+hipError_t fields_generic_t(const SimConst *c, int nx, int ny, int nz, const void *g, double *rho_f,
                             double *psi_f, double *s_f, double *j_f, double *u_f,
                             uint32_t *status, hipStream_t st) {
-    const unsigned nb = nblocks(ns);
+    const unsigned nb = nblocks((int64_t)nx * ny * nz);
     hipLaunchKernelGGL((k_moments_eos<L, ST>), dim3(nb), dim3(TPB), 0, st, c, g, rho_f, psi_f,
                        s_f, j_f, status);
     hipLaunchKernelGGL((k_interface<L>), dim3(nb), dim3(TPB), 0, st, c, s_f, psi_f);
-    if (u_f)
-        hipLaunchKernelGGL((k_velocity<L>), dim3(nb), dim3(TPB), 0, st, c, rho_f, psi_f, j_f,
+    if (u_f) {
+        const unsigned vb = unit_blocks(TileGeom<L, TileV<L>>::count(nx, ny, nz));
+        hipLaunchKernelGGL((k_velocity_t<L>), dim3(vb), dim3(TPB), 0, st, c, rho_f, psi_f, j_f,
                            u_f);
+    }
     return hipGetLastError();
 }
 
@@ -630,25 +626,27 @@ hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int nc
                 : step_generic_t<D3Q19, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
 }
 
-hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int64_t ns, const void *g,
-                         double *rho_f, double *psi_f, double *s_f, double *j_f, double *u_f,
-                         uint32_t *status, hipStream_t st) {
+hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int nx, int ny, int nz,
+                         const void *g, double *rho_f, double *psi_f, double *s_f, double *j_f,
+                         double *u_f, uint32_t *status, hipStream_t st) {
     if (lattice == 0)
-        return fp32 ? fields_generic_t<D2Q9, float>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st)
-                    : fields_generic_t<D2Q9, double>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st);
-    return fp32 ? fields_generic_t<D3Q19, float>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st)
-                : fields_generic_t<D3Q19, double>(c, ns, g, rho_f, psi_f, s_f, j_f, u_f, status, st);
+        return fp32 ? fields_generic_t<D2Q9, float>(c, nx, ny, nz, g, rho_f, psi_f, s_f, j_f, u_f, status, st)
+                    : fields_generic_t<D2Q9, double>(c, nx, ny, nz, g, rho_f, psi_f, s_f, j_f, u_f, status, st);
+    return fp32 ? fields_generic_t<D3Q19, float>(c, nx, ny, nz, g, rho_f, psi_f, s_f, j_f, u_f, status, st)
+                : fields_generic_t<D3Q19, double>(c, nx, ny, nz, g, rho_f, psi_f, s_f, j_f, u_f, status, st);
 }
 
-hipError_t launch_diag(int lattice, bool fp32, const SimConst *c, int64_t /*ns*/, const void *g,
-                       double *snap, double *part, int nblk, int use_snap, hipStream_t st) {
-    if (lattice == 0) {
-        if (fp32) hipLaunchKernelGGL((k_diag<D2Q9, float>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
-        else hipLaunchKernelGGL((k_diag<D2Q9, double>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
-    } else {
-        if (fp32) hipLaunchKernelGGL((k_diag<D3Q19, float>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
-        else hipLaunchKernelGGL((k_diag<D3Q19, double>), dim3(nblk), dim3(TPB), 0, st, c, g, snap, part, use_snap);
-    }
+hipError_t launch_diag(int dim, int ncomp, int64_t ns, const double *rho_f, const double *j_f,
+                       const double *u_f, double *snap, double *part, int nblk, double *out,
+                       int use_snap, hipStream_t st) {
+    const dim3 grid(nblk, ncomp + 1);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_diag_part<2>, grid, dim3(TPB), 0, st, ncomp, ns, rho_f, j_f, u_f,
+                           snap, part, use_snap);
+    else
+        hipLaunchKernelGGL(k_diag_part<3>, grid, dim3(TPB), 0, st, ncomp, ns, rho_f, j_f, u_f,
+                           snap, part, use_snap);
+    hipLaunchKernelGGL(k_diag_final, dim3(ncomp + 1), dim3(TPB), 0, st, part, nblk, out);
     return hipGetLastError();
 }
 

@@ -179,14 +179,25 @@ class Server:
 
 
 def latency_stats(done):
-    lat = np.array([r.finish_t - r.arrival for r in done if r.status == 0])
-    svc = np.array([r.finish_t - r.admit_t for r in done if r.status == 0])
-    if lat.size == 0:
-        return dict(n=0)
-    return dict(n=int(lat.size), p50_s=float(np.percentile(lat, 50)),
-                p99_s=float(np.percentile(lat, 99)), service_p50_s=float(np.percentile(svc, 50)),
-                service_p99_s=float(np.percentile(svc, 99)),
-                converged=int(sum(r.converged for r in done)))
+    """Time-to-equilibrium statistics over the requests that converged
+    (R_K <= tol); a request retired at its step cap is counted as capped,
+    not converged, and enters no percentile; failed requests (non-zero
+    status) are counted apart."""
+    conv = [r for r in done if r.status == 0 and r.converged]
+    capped = [r for r in done if r.status == 0 and not r.converged]
+    failed = [r for r in done if r.status != 0]
+    out = dict(requests=len(done), converged=len(conv), capped=len(capped), failed=len(failed))
+    if conv:
+        lat = np.array([r.finish_t - r.arrival for r in conv])
+        svc = np.array([r.finish_t - r.admit_t for r in conv])
+        steps = np.array([r.steps for r in conv])
+        out.update(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                   service_p50_s=float(np.percentile(svc, 50)),
+                   service_p99_s=float(np.percentile(svc, 99)),
+                   steps_p50=int(np.percentile(steps, 50)), steps_max=int(steps.max()))
+    if capped:
+        out["capped_residual_max"] = float(max(r.residual for r in capped))
+    return out
 
 
 def pool_requests(states, count, rate_hz, seed=5, precision=capi.FP32_STORAGE, tol=1e-8,

@@ -166,7 +166,11 @@ def test_server_alone_equals_mix_and_budget():
         assert r.status == 0 and r.steps == a.steps
         assert np.array_equal(r.result["populations"], a.result["populations"])
     st = serve.latency_stats(done)
-    assert st["n"] == len(mix) and st["p99_s"] >= st["p50_s"] > 0
+    nconv = sum(r.converged for r in done)
+    assert st["requests"] == len(mix) and st["converged"] == nconv
+    assert st["capped"] == len(mix) - nconv and st["failed"] == 0
+    if nconv:
+        assert st["p99_s"] >= st["p50_s"] > 0
 
 
 def test_server_isolates_a_failing_request():
