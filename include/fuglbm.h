@@ -171,6 +171,25 @@ fuglbm_status fuglbm_step_n(fuglbm_sim *sim, int64_t nsteps, void *hip_stream);
 fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count, int64_t nsteps,
                                void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batched step as fuglbm_step_many, with bitwise the same results, that
+ * allocates nothing.  Its work tables live in a fixed device array of the
+ * library (1.06 MB per GPU, held until the process ends) and are written
+ * by a small table kernel on hip_stream from the call's arguments; each
+ * step is one plain launch of the fused kernel per (ncomp, precision)
+ * class of members (no graph, no tuning: every member keeps its current
+ * fused variant and rows per work item).
+ * Limits: at most 256 simulations and 65536 fused work items per call
+ * (EINVAL beyond); every member must be a D2Q9 simulation on a fused
+ * kernel (EINVAL otherwise).  Members with a sticky device error are
+ * skipped and ENONFINITE is returned after the others have been stepped.
+ * Every call on one GPU shares the array: calls that overlap on one GPU
+ * (other streams or threads before this call's launches have finished)
+ * race and must not be made. */
+fuglbm_status fuglbm_step_many_noalloc(fuglbm_sim *const *sims, int32_t count, int64_t nsteps,
+                                       void *hip_stream);
+
 /* Synchronise and read macroscopic fields: rho_out host [ncomp][sites] (or
  * NULL), u_out host [D][sites] force-corrected velocity (or NULL), diag (or
  * NULL; as fuglbm_diagnostics).  Returns ENONFINITE if a status bit is set

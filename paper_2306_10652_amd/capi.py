@@ -29,6 +29,7 @@ EXPORTED = [
     "fuglbm_read_moments", "fuglbm_diagnostics", "fuglbm_read_populations",
     "fuglbm_write_populations", "fuglbm_set_tuning", "fuglbm_get_tuning", "fuglbm_sim_info",
     "fuglbm_poke_population", "fuglbm_destroy_sim", "fuglbm_last_error",
+    "fuglbm_step_many_noalloc",
 ]
 
 
@@ -91,6 +92,7 @@ def lib():
         "fuglbm_init_fields": ([vp, i32, i32, i32, i32, i32, dp, vp, vp, ctypes.POINTER(vp)], i32),
         "fuglbm_step_n": ([vp, i64, vp], i32),
         "fuglbm_step_many": ([ctypes.POINTER(vp), i32, i64, vp], i32),
+        "fuglbm_step_many_noalloc": ([ctypes.POINTER(vp), i32, i64, vp], i32),
         "fuglbm_read_moments": ([vp, dp, dp, ctypes.POINTER(Diag)], i32),
         "fuglbm_diagnostics": ([vp, ctypes.POINTER(Diag)], i32),
         "fuglbm_read_populations": ([vp, dp], i32),
@@ -295,3 +297,11 @@ def fuglbm_step_many(sims, nsteps, stream=None):
 def step_many(sims, nsteps, stream=None):
     check(fuglbm_step_many(sims, nsteps, stream))
 
+
+def fuglbm_step_many_noalloc(sims, nsteps, stream=None):
+    arr = (ctypes.c_void_p * len(sims))(*[s.handle.value for s in sims])
+    return lib().fuglbm_step_many_noalloc(arr, len(sims), int(nsteps), _stream_ptr(stream))
+
+
+def step_many_noalloc(sims, nsteps, stream=None):
+    check(fuglbm_step_many_noalloc(sims, nsteps, stream))

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1192,6 +1193,211 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
     for (auto *s : others) {
         fuglbm_status rc = fuglbm_step_n(s, nsteps, hip_stream);
         if (rc != FUGLBM_OK) return rc;
+    }
+    if (skipped) return fail(FUGLBM_ENONFINITE, "some simulations have a sticky device error");
+    return FUGLBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched stepping without allocation (fuglbm_step_many_noalloc).
+//
+// The batch's work tables (per-member pointers and geometry, then the work
+// items in the same XCD-dealt order as fuglbm_step_many) live in `scratch`,
+// a file-scope device array of fixed size that every call on a device
+// shares.  They are written on the device by a table kernel whose member
+// data arrive as kernel arguments, so a call needs no device allocation,
+// no graph instantiation and no copy from host memory; the steps are plain
+// launches of the fused kernel.  `scratch` is a host-side stand-in in host
+// code: its device address is looked up once per device
+// (hipGetSymbolAddress) and only that address is ever passed on.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int NA_MAX_MEMBERS = 256;                // simulations per call
+constexpr int NA_MAX_ITEMS = 65536;                // fused work items per call
+constexpr int NA_CHUNK = 32;                       // members per table-kernel launch
+constexpr size_t NA_GEOM_OFF = 0;                  // int4 {nx, ny, rows, first item}
+constexpr size_t NA_SIMS_OFF = NA_GEOM_OFF + 16 * NA_MAX_MEMBERS;
+constexpr size_t NA_ITEMS_OFF = NA_SIMS_OFF + sizeof(FusedSim) * NA_MAX_MEMBERS;
+constexpr size_t NA_SCRATCH_BYTES = NA_ITEMS_OFF + sizeof(FusedItem) * NA_MAX_ITEMS;
+
+static __device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];
+
+struct NaMember {
+    const SimConst *c;
+    void *buf0, *buf1;
+    uint32_t *status;
+    int32_t parity, nx, ny, rows;
+};
+
+struct NaChunk {
+    int32_t base;                 // index of m[0] among the group's members
+    int32_t count;                // members in this chunk
+    int32_t first[NA_CHUNK];      // each member's first logical item in the group
+    NaMember m[NA_CHUNK];
+};
+
+// Members [base, base + count) of one group: pointers and geometry.
+__global__ void k_na_members(NaChunk a, FusedSim *sims, int4 *geom) {
+    const int t = threadIdx.x;
+    if (t >= a.count) return;
+    const NaMember &m = a.m[t];
+    FusedSim fs;
+    fs.c = m.c;
+    fs.buf[0] = m.buf0;
+    fs.buf[1] = m.buf1;
+    fs.status = m.status;
+    fs.parity = m.parity;
+    fs.pad = 0;
+    sims[a.base + t] = fs;
+    geom[a.base + t] = make_int4(m.nx, m.ny, m.rows, a.first[t]);
+}
+
+// Work items of one group: logical item li (member-major, then chunk of
+// rows, then strip) goes to slot (li % per) * 8 + li / per, so XCD k
+// (workgroups are dealt round-robin) runs the k-th contiguous slice.
+__global__ void k_na_items(const int4 *geom, int nmem, int nlogical, int per, FusedItem *items) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= per * 8) return;
+    const int li = (b % 8) * per + b / 8;
+    FusedItem it{-1, 0, 0, 0};
+    if (li < nlogical) {
+        int k = 0;
+        while (k + 1 < nmem && geom[k + 1].w <= li) ++k;
+        const int4 g = geom[k];
+        const int strips = (g.x + FUSED_OUT - 1) / FUSED_OUT;
+        const int local = li - g.w;
+        const int c = local / strips, t = local % strips;
+        it.sim = k;
+        it.x0 = t * FUSED_OUT;
+        it.y0 = c * g.z;
+        it.rows = min(g.z, g.y - c * g.z);
+    }
+    items[b] = it;
+}
+
+std::mutex na_mutex;
+void *na_ptr[64];
+
+// Device address of `scratch` on the current device (looked up once).
+fuglbm_status na_scratch(char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(FUGLBM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(na_mutex);
+    if (!na_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        na_ptr[dev] = p;
+    }
+    *out = (char *)na_ptr[dev];
+    return FUGLBM_OK;
+}
+
+}  // namespace
+
+extern "C" fuglbm_status fuglbm_step_many_noalloc(fuglbm_sim *const *sims, int32_t count,
+                                                  int64_t nsteps, void *hip_stream) {
+    if (count < 0 || (count > 0 && !sims)) return fail(FUGLBM_EINVAL, "bad sims array");
+    if (nsteps < 0) return fail(FUGLBM_EINVAL, "nsteps must be >= 0");
+    if (count > NA_MAX_MEMBERS)
+        return fail(FUGLBM_EINVAL, "at most 256 simulations per call");
+    hipStream_t st = (hipStream_t)hip_stream;
+    // members by (ncomp, precision) class, in call order; sticky ones skipped
+    int cls[NA_MAX_MEMBERS];
+    int key[NA_MAX_MEMBERS], nkeys = 0;
+    bool skipped = false;
+    int64_t total_items = 0;
+    for (int k = 0; k < count; ++k) {
+        fuglbm_sim *s = sims[k];
+        if (!s) return fail(FUGLBM_EINVAL, "null sim in batch");
+        for (int q = 0; q < k; ++q)
+            if (sims[q] == s) return fail(FUGLBM_EINVAL, "duplicate sim in batch");
+        if (s->lattice != FUGLBM_D2Q9 || s->kernel < 2)
+            return fail(FUGLBM_EINVAL, "only D2Q9 simulations on a fused kernel");
+        if (s->rows < 1) return fail(FUGLBM_EINVAL, "simulation without fused rows");
+        cls[k] = -1;
+        if (s->sticky) {
+            skipped = true;
+            continue;
+        }
+        const int kk = s->N * 2 + (s->fp32 ? 1 : 0);
+        int g = 0;
+        while (g < nkeys && key[g] != kk) ++g;
+        if (g == nkeys) key[nkeys++] = kk;
+        cls[k] = g;
+        const int64_t strips = (s->nx + FUSED_OUT - 1) / FUSED_OUT;
+        total_items += strips * ((s->ny + s->rows - 1) / s->rows) + 7;   // + XCD padding
+    }
+    if (total_items > NA_MAX_ITEMS)
+        return fail(FUGLBM_EINVAL, "batch needs more than 65536 work items");
+    if (nkeys == 0 || nsteps == 0) {
+        if (skipped) return fail(FUGLBM_ENONFINITE, "some simulations have a sticky device error");
+        return FUGLBM_OK;
+    }
+    char *base = nullptr;
+    fuglbm_status rc = na_scratch(&base);
+    if (rc != FUGLBM_OK) return rc;
+    int4 *geom = (int4 *)(base + NA_GEOM_OFF);
+    FusedSim *dsims = (FusedSim *)(base + NA_SIMS_OFF);
+    FusedItem *ditems = (FusedItem *)(base + NA_ITEMS_OFF);
+    int mem_off = 0, item_off = 0;
+    for (int g = 0; g < nkeys; ++g) {
+        // this group's members, their first logical items
+        NaChunk ch;
+        int nmem = 0, nlogical = 0;
+        fuglbm_sim *first = nullptr;
+        ch.base = 0;
+        ch.count = 0;
+        for (int k = 0; k < count; ++k) {
+            if (cls[k] != g) continue;
+            fuglbm_sim *s = sims[k];
+            if (!first) first = s;
+            NaMember &m = ch.m[ch.count];
+            m.c = s->dc;
+            m.buf0 = s->buf[0];
+            m.buf1 = s->buf[1];
+            m.status = s->status;
+            m.parity = s->parity;
+            m.nx = s->nx;
+            m.ny = s->ny;
+            m.rows = s->rows;
+            ch.first[ch.count] = nlogical;
+            nlogical += ((s->nx + FUSED_OUT - 1) / FUSED_OUT) * ((s->ny + s->rows - 1) / s->rows);
+            ++ch.count;
+            ++nmem;
+            if (ch.count == NA_CHUNK) {
+                hipLaunchKernelGGL(k_na_members, dim3(1), dim3(NA_CHUNK), 0, st, ch,
+                                   dsims + mem_off, geom + mem_off);
+                ch.base += NA_CHUNK;
+                ch.count = 0;
+            }
+        }
+        if (ch.count > 0)
+            hipLaunchKernelGGL(k_na_members, dim3(1), dim3(NA_CHUNK), 0, st, ch, dsims + mem_off,
+                               geom + mem_off);
+        const int per = (nlogical + 7) / 8;
+        const int nitems = per * 8;
+        hipLaunchKernelGGL(k_na_items, dim3((nitems + 255) / 256), dim3(256), 0, st,
+                           geom + mem_off, nmem, nlogical, per, ditems + item_off);
+        HIP_TRY(hipGetLastError());
+        const int ncomp = first->N;
+        const bool f32 = first->fp32;
+        const int kern = first->kernel == 3 && ws_usable(ncomp, f32) ? 3 : 2;
+        for (int64_t t = 0; t < nsteps; ++t) {
+            hipError_t e = launch_fused(kern, ncomp, f32, ditems + item_off, nitems,
+                                        dsims + mem_off, (int)(t & 1), st);
+            if (e != hipSuccess) return hip_fail(e, "batched step launch");
+        }
+        mem_off += nmem;
+        item_off += nitems;
+    }
+    for (int k = 0; k < count; ++k) {
+        if (cls[k] < 0) continue;
+        fuglbm_sim *s = sims[k];
+        s->parity ^= (int)(nsteps & 1);
+        s->step += nsteps;
+        s->last_stream = st;
     }
     if (skipped) return fail(FUGLBM_ENONFINITE, "some simulations have a sticky device error");
     return FUGLBM_OK;
