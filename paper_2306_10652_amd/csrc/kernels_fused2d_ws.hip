@@ -18,11 +18,21 @@
 //    the registers of a row in flight are never copied (a copy would have
 //    to wait for the load).
 //
+//  * The two store wavefronts also compute every per-site term that needs
+//    all components (the helper work): the cubic-EOS mixture coefficients
+//    of row r-1 (reciprocals and Z - 1 on store wave 0, the logarithmic
+//    term on store wave 1) while the component waves collide and take
+//    moments, and the sums over components of row r (b_m rt and rt; 1/rho
+//    and j) after their stores.  The component waves then do the same work
+//    between barriers, and the EOS chain is off their critical path.
+//
 // Per lead row r (output row y = r - 2):
-//   1  (component waves) moments of row r; G_i(y); helper mixture terms
+//      (store waves) mixture coefficients of row r - 1
+//   1  (component waves) moments of row r; G_i(y)
 //   -- barrier --
-//      (store waves) write the staged output row of lead row r - 1
-//   2  (component waves) s, psi_i(r-1), F_i(y), Sraw_i(r), helper sums
+//      (store waves) write the staged output row of lead row r - 1; sums
+//      over components of row r
+//   2  (component waves) s, psi_i(r-1), F_i(y), Sraw_i(r)
 //   -- barrier --
 //   3  (component waves) u(y), collision of row y -> LDS staging; row
 //      r-1 stash -> registers, row r -> stash, request row r+3
@@ -58,7 +68,7 @@ struct Comp {
     gptr<ST> src[8];
     uint32_t rsr, rsm;
     int comp, lane, xc, y0;
-    double invM, bi, sqki, RT, invRT, omega, fcoef;
+    double invM, bi, sqki, RT, omega, fcoef;
     uint32_t bad;
 
     // One row's nine loads, kept together and in program order (neither
@@ -75,10 +85,9 @@ struct Comp {
         __builtin_amdgcn_sched_barrier(0);
     }
 
-    // ---- phase 1: moments of row r (gC); G_i of row y; mixture terms of row r-1
+    // ---- phase 1: moments of row r (gC); G_i of row y
     __device__ __forceinline__ void phase1(int r, const PopRow<ST> &gC, double rhm3, double rhm2,
                                            double rhm1, double &rh0, double &Gx, double &Gy) {
-        const bool do_eos = r >= y0;
         const bool do_out = r >= y0 + 2;
         {
             double v[9];
@@ -96,37 +105,9 @@ struct Comp {
         Gx = 0.0;
         Gy = 0.0;
         if (do_out) grad3(rhm3, rhm2, rhm1, Gx, Gy);
-        // Eq. (9)-(12), combined-log form, for row r-1 (see the register-ring
-        // kernel): helper A reciprocals and Z - 1, helper B the log term.
-        if (do_eos && comp == helper_wave<NC>(0)) {
-            const int ms = (r - 1) & 1;
-            const double rt1 = L.mx[ms][0][lane];
-            const double et1 = L.mx[ms][1][lane];
-            double xsum = 0.0;
-#pragma unroll
-            for (int j = 0; j < NC; ++j) xsum += L.xs[j][lane];
-            const double inv_rt = frcp(rt1);
-            const double am = xsum * inv_rt * inv_rt;
-            const double ome = 1.0 - et1;
-            if (!(ome > 0.0)) bad |= FUG_ST_COVOLUME;
-            const double inv_ome = frcp(ome);
-            const double inv_bm = rt1 * frcp(et1);
-            const double den = 1.0 + C->eu * et1 + C->ew * et1 * et1;
-            const double zm1 = et1 * inv_ome - am * rt1 * invRT * frcp(den);
-            L.eos[0][lane] = RT * inv_ome;
-            L.eos[1][lane] = RT * zm1 * inv_bm;
-            L.eos[2][lane] = am * inv_bm * inv_bm;
-            L.eos[3][lane] = 2.0 * inv_bm * inv_rt;
-        }
-        if (do_eos && comp == helper_wave<NC>(1)) {
-            const double et1 = L.mx[(r - 1) & 1][1][lane];
-            L.eos[4][lane] = C->eos == 2
-                                 ? et1
-                                 : log((1.0 + C->d1 * et1) * frcp(1.0 + C->d2 * et1)) * C->dk;
-        }
     }
 
-    // ---- phase 2: s(r); psi_i(r-1); F_i(y); Sraw_i(r); helper sums of row r
+    // ---- phase 2: s(r); psi_i(r-1); F_i(y); Sraw_i(r)
     __device__ __forceinline__ void phase2(int r, double rhm2, double rhm1, double rh0,
                                            double psm3, double psm2, double &psm1, double svm2,
                                            double svm1, double &sv0, double &sn, double so,
@@ -168,29 +149,6 @@ struct Comp {
             for (int j = 0; j < NC; ++j) acc += arow[j] * L.rt[j][lane];
             sn = acc;
             L.xs[comp][lane] = rh0 * invM * acc;
-        }
-        if (do_s && comp == helper_wave<NC>(2)) {
-            double rtt = 0.0, eta = 0.0;
-#pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                const double t = L.rt[j][lane];
-                rtt += t;
-                eta += C->b[j] * t;
-            }
-            L.mx[r & 1][0][lane] = rtt;
-            L.mx[r & 1][1][lane] = eta;
-        }
-        if (comp == helper_wave<NC>(3)) {
-            double rtot = 0.0, jxt = 0.0, jyt = 0.0;
-#pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                rtot += C->M[j] * L.rt[j][lane];
-                jxt += L.jx[j][lane];
-                jyt += L.jy[j][lane];
-            }
-            L.tot[r & 3][0][lane] = frcp(rtot);
-            L.tot[r & 3][1][lane] = jxt;
-            L.tot[r & 3][2][lane] = jyt;
         }
     }
 
@@ -262,12 +220,16 @@ template <int NC, typename ST>
 struct Store {
     static constexpr int CPW = (NC + STORE_WAVES - 1) / STORE_WAVES;
     WsLds<NC, ST> &W;
+    FusedLds<NC> &L;
+    cptr<SimConst> C;
     char *bdst;
     PopLayout<ST> P;
     uint32_t rsr, rsm;
-    int sw, nx, ny;
+    int sw, nx, ny, y0;
     int xsh[3];     // destination column for ex = -1, 0, +1
     bool outl;
+    double RT, invRT;
+    uint32_t bad;
 
     __device__ __forceinline__ void row(int yw) const {
         if (!outl) return;
@@ -302,6 +264,69 @@ struct Store {
             }
         }
     }
+
+    // Eq. (9)-(12), combined-log form, mixture coefficients of row r-1 (the
+    // register-ring kernel computes the same terms on its helper
+    // wavefronts): store wave 0 the reciprocals and Z - 1, store wave 1
+    // the logarithmic term.  Status bits only for lead rows <= last (the
+    // rows past it repeat the item's last loaded row).
+    __device__ __forceinline__ void mixture(int r, int last) {
+        if (r < y0) return;
+        const int lane = threadIdx.x & 63;
+        const double et1 = L.mx[(r - 1) & 1][1][lane];
+        if (sw == 0) {
+            const double rt1 = L.mx[(r - 1) & 1][0][lane];
+            double xsum = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) xsum += L.xs[j][lane];
+            const double inv_rt = frcp(rt1);
+            const double am = xsum * inv_rt * inv_rt;
+            const double ome = 1.0 - et1;
+            if (!(ome > 0.0) && r <= last) bad |= FUG_ST_COVOLUME;
+            const double inv_ome = frcp(ome);
+            const double inv_bm = rt1 * frcp(et1);
+            const double den = 1.0 + C->eu * et1 + C->ew * et1 * et1;
+            const double zm1 = et1 * inv_ome - am * rt1 * invRT * frcp(den);
+            L.eos[0][lane] = RT * inv_ome;
+            L.eos[1][lane] = RT * zm1 * inv_bm;
+            L.eos[2][lane] = am * inv_bm * inv_bm;
+            L.eos[3][lane] = 2.0 * inv_bm * inv_rt;
+        } else {
+            L.eos[4][lane] = C->eos == 2
+                                 ? et1
+                                 : log((1.0 + C->d1 * et1) * frcp(1.0 + C->d2 * et1)) * C->dk;
+        }
+    }
+
+    // Sums over components of row r: rt and b_m rt (store wave 0, for the
+    // mixture coefficients of the next lead row), 1/rho and j (store wave 1,
+    // for the velocity two rows later).
+    __device__ __forceinline__ void sums(int r) {
+        const int lane = threadIdx.x & 63;
+        if (sw == 0) {
+            if (r < y0 - 1) return;
+            double rtt = 0.0, eta = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const double t = L.rt[j][lane];
+                rtt += t;
+                eta += C->b[j] * t;
+            }
+            L.mx[r & 1][0][lane] = rtt;
+            L.mx[r & 1][1][lane] = eta;
+        } else {
+            double rtot = 0.0, jxt = 0.0, jyt = 0.0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                rtot += C->M[j] * L.rt[j][lane];
+                jxt += L.jx[j][lane];
+                jyt += L.jy[j][lane];
+            }
+            L.tot[r & 3][0][lane] = frcp(rtot);
+            L.tot[r & 3][1][lane] = jxt;
+            L.tot[r & 3][2][lane] = jyt;
+        }
+    }
 };
 
 template <int NC, typename ST>
@@ -330,8 +355,9 @@ __global__ __launch_bounds__(64 * (NC + STORE_WAVES)) void k_fused_d2q9_ws(
     // Every wave runs the same loop (same barrier count); a pass of the
     // unrolled body handles lead rows r, r+1, r+2, up to rend + 1 (the flush).
     if (wave >= NC) {
-        Store<NC, ST> s{lds, bdst, P, (uint32_t)P.rest_row_stride(), (uint32_t)P.move_row_stride(),
-                        wave - NC, nx, ny, {0, 0, 0}, false};
+        Store<NC, ST> s{lds, lds.f, C, bdst, P, (uint32_t)P.rest_row_stride(),
+                        (uint32_t)P.move_row_stride(), wave - NC, nx, ny, it.y0, {0, 0, 0},
+                        false, C->RT, 1.0 / C->RT, 0u};
         s.xsh[0] = xc == 0 ? nx - 1 : xc - 1;
         s.xsh[1] = xc;
         s.xsh[2] = xc == nx - 1 ? 0 : xc + 1;
@@ -342,12 +368,15 @@ __global__ __launch_bounds__(64 * (NC + STORE_WAVES)) void k_fused_d2q9_ws(
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const int r = r0 + k;
+                s.mixture(r, rend);
                 __syncthreads();
                 if (r - 1 >= it.y0 + 2 && r - 1 <= rend) s.row(yw);
+                s.sums(r);
                 yw = yw + 1 == ny ? 0 : yw + 1;
                 __syncthreads();
             }
         }
+        if (s.bad) atomicOr(sm->status, s.bad);
         return;
     }
 
@@ -366,7 +395,6 @@ __global__ __launch_bounds__(64 * (NC + STORE_WAVES)) void k_fused_d2q9_ws(
     f.bi = C->b[f.comp];
     f.sqki = C->sqk[f.comp];
     f.RT = C->RT;
-    f.invRT = 1.0 / C->RT;
     f.omega = C->omega;
     f.fcoef = C->fcoef;
     f.bad = 0;
