@@ -493,37 +493,81 @@ def _golden_ten_co2():
         return json.load(f)
 
 
+def _ten_co2_phase_errors(om, vap, liq, z, p):
+    """Relative errors (%) of the bulk phases against the oracle's flash at
+    (T, p, z): mass density, then each mole fraction."""
+    from oracle import thermo as th
+    r = th.flash(om.pr, z, p)
+    out = {}
+    for ph, b, fr, fx in (("V", vap, r.y * r.rhoV, r.y), ("L", liq, r.x * r.rhoL, r.x)):
+        x = b / b.sum()
+        out[ph] = [100 * abs(float(b @ om.M) / float(fr @ om.M) - 1)] + list(100 * np.abs(x / fx - 1))
+    return out
+
+
 def test_ten_component_flat_interface_against_flash_table_viii():
     """Section III.E, Table VIII: the ten-component CO2 mixture (Table VII,
-    k_ij with CO2) at 325 K and 150 bar on a 400 x 2 slab, 10^6 steps as in
-    the paper; bulk phases against the flash at the same conditions.  The
-    paper's errors are 0.005 % - 0.51 %; ours (0.03 % - 0.99 %, largest for
-    the heaviest fraction) must stay within 1.5 %."""
+    k_ij with CO2) at 325 K and 150 bar on a 400 x 2 slab from Eq. (15) at
+    the flash state.  After the paper's 10^6 steps, the bulk phases (8-column
+    windows) against the flash at the LBM's vapour-bulk pressure and the
+    initial overall composition (the comparison of Section III.B, Table IV)
+    reproduce every entry of Table VIII within 0.01 percentage points
+    (measured <= 0.002; worst entry C7+ in the liquid, 0.512 % against the
+    paper's 0.511 %).  The slab is still relaxing then (residual ~4e-9);
+    continued to 4 x 10^6 steps (residual over the last 10^4 steps < 1e-10)
+    the phases lie on their own tie line: a flash at the LBM pressure and
+    z = (x^V + x^L) / 2 matches them within 0.05 %.  (Against the flash at the nominal 150 bar
+    the 10^6-step errors reach 0.99 %, reported.)"""
     capi = _capi()
     st, mix, om = _ten_co2(325.0)
     n = 400
     rho = Fi.slab(n, 2, st["rho_V"], st["rho_L"], st["S_V"])
-    out = run_to_equilibrium(mix, (n, 2), rho, 0.0, 1000000, chunk=100000)
-    rt = out["rho"][:, 0, :, :] / om.M[:, None, None]
-    vap = np.concatenate([rt[:, :, 0:8], rt[:, :, n - 8:n]], axis=2).mean(axis=(1, 2))
-    liq = rt[:, :, n // 2 - 8:n // 2 + 8].mean(axis=(1, 2))
-    M = np.array([c.M for c in C.TEN_CO2])
-    errs = {}
-    for ph, b, xf, rf in (("V", vap, np.array(st["y"]), np.array(st["rho_V"])),
-                          ("L", liq, np.array(st["x"]), np.array(st["rho_L"]))):
-        mass_lbm, mass_flash = float(np.sum(b * om.M)), float(np.sum(rf))
-        errs[ph] = dict(rho=100 * abs(mass_lbm / mass_flash - 1),
-                        x=(100 * np.abs((b / b.sum()) / xf - 1)).tolist())
-    g = _golden_ten_co2()["table_viii_percent"]
-    # report in the paper's component order (CO2 first)
-    order = [C.TEN_CO2_NAMES.index(nm) for nm in _golden_ten_co2()["components"]]
-    report("ten_co2_flat", steps=out["steps"],
-           rho_err_pct=(errs["V"]["rho"], errs["L"]["rho"]), paper_rho_err_pct=(g["rho"]["V"], g["rho"]["L"]),
-           xV_err_pct=[round(errs["V"]["x"][k], 4) for k in order], paper_xV=g["x"]["V"],
-           xL_err_pct=[round(errs["L"]["x"][k], 4) for k in order], paper_xL=g["x"]["L"])
-    worst = max(errs["V"]["rho"], errs["L"]["rho"], max(errs["V"]["x"]), max(errs["L"]["x"]))
+    sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (n, 2), rho)
+    z0 = np.array(C.TEN_CO2_Z) / np.sum(C.TEN_CO2_Z)
+    g = _golden_ten_co2()
+    order = [C.TEN_CO2_NAMES.index(nm) for nm in g["components"]]
+
+    def bulk():
+        rt = sim.read_moments(velocity=False)["rho"][:, 0, :, :] / om.M[:, None, None]
+        prof = rt.mean(axis=1)
+        vap = np.concatenate([prof[:, 0:8], prof[:, n - 8:n]], axis=1).mean(axis=1)
+        liq = prof[:, n // 2 - 8:n // 2 + 8].mean(axis=1)
+        return vap, liq
+
+    sim.diagnostics()
+    sim.step_n(1000000)
+    d = sim.diagnostics()
+    assert d["rc"] == 0
+    vap, liq = bulk()
+    p_lbm = om.pr.pressure_rho(vap)
+    errs = _ten_co2_phase_errors(om, vap, liq, z0, p_lbm)
+    nominal = _ten_co2_phase_errors(om, vap, liq, z0, om.units.p(150.0 * 1e5))
+    t8 = g["table_viii_percent"]
+    worst_dev = 0.0
+    for ph in ("V", "L"):
+        ours = [errs[ph][0]] + [errs[ph][1 + k] for k in order]
+        paper = [t8["rho"][ph]] + t8["x"][ph]
+        report("ten_co2_table_viii", phase=ph, ours=[round(v, 4) for v in ours], paper=paper)
+        worst_dev = max(worst_dev, max(abs(a - b) for a, b in zip(ours, paper)))
+    report("ten_co2_flat", steps=d["step"], residual=d["residual"],
+           p_lbm_bar=p_lbm / om.units.p(1e5), max_dev_from_paper_pct_points=worst_dev,
+           worst_pct=max(max(errs["V"]), max(errs["L"])),
+           nominal_150bar_worst_pct=max(max(nominal["V"]), max(nominal["L"])))
+    assert worst_dev <= 0.01
+    # relaxed to its own equilibrium (residual over the last 10^4 steps)
+    sim.step_n(2990000)
+    sim.diagnostics()
+    sim.step_n(10000)
+    d = sim.diagnostics()
+    assert d["rc"] == 0 and d["residual"] < 1e-10
+    vap, liq = bulk()
+    zmid = 0.5 * (vap / vap.sum() + liq / liq.sum())
+    own = _ten_co2_phase_errors(om, vap, liq, zmid, om.pr.pressure_rho(vap))
+    worst_own = max(max(own["V"]), max(own["L"]))
+    report("ten_co2_equilibrium", steps=d["step"], residual=d["residual"], own_tie_line_worst_pct=worst_own)
+    sim.close()
     mix.close()
-    assert worst < 1.5
+    assert worst_own < 0.05
 
 
 def _window_extremes(field, w=4):
@@ -544,8 +588,9 @@ def test_ten_component_spinodal_iso_fugacity_tables_ix_x(case, T):
     150 bar lever-rule density with 1 % noise, decomposes on 200 x 200 over
     500 000 steps; the fugacity of every component is the same in the
     liquid and vapour regions (4 x 4 windows at the densest and lightest
-    spots).  The paper's ratios f_L / f_V lie within 1.4 % of one; ours must
-    lie within 2 %."""
+    spots).  The paper's ratios f_L / f_V lie within 1.4 % of one (Table X,
+    C7+: 0.986397); ours must too (measured 1.1 % in Case 1, 0.5 % in
+    Case 2)."""
     capi = _capi()
     st, mix, om = _ten_co2(T)
     n = 200
@@ -570,7 +615,7 @@ def test_ten_component_spinodal_iso_fugacity_tables_ix_x(case, T):
     mix.close()
     # both phases present: molar density ratio of the windows near the flash's
     assert abs((liq.sum() / vap.sum()) / flash_ratio - 1) < 0.05
-    assert np.max(np.abs(ratio - 1)) < 0.02
+    assert np.max(np.abs(ratio - 1)) < 0.014
 
 
 def _drop_dp(sim, om, n, D):
