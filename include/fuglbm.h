@@ -67,8 +67,11 @@ typedef enum {
     FUGLBM_ESTATE = 6         /* call not valid in the handle's state (mixed lattice in a batch, ...) */
 } fuglbm_status;
 
-typedef enum { FUGLBM_D2Q9 = 0, FUGLBM_D3Q19 = 1 } fuglbm_lattice;
-typedef enum { FUGLBM_FP64 = 0, FUGLBM_FP32_STORAGE = 1 } fuglbm_precision;
+/* The last enumerator of each input enum only widens it to 32 bits, so
+ * that any int a C caller passes is a valid value of the type (the library
+ * rejects values other than the named ones with EINVAL). */
+typedef enum { FUGLBM_D2Q9 = 0, FUGLBM_D3Q19 = 1, FUGLBM_LATTICE_INT32_ = 0x7fffffff } fuglbm_lattice;
+typedef enum { FUGLBM_FP64 = 0, FUGLBM_FP32_STORAGE = 1, FUGLBM_PRECISION_INT32_ = 0x7fffffff } fuglbm_precision;
 
 /* Cubic equation of state p = RT/(v - b) - a alpha / ((v + d1 b)(v + d2 b)).
  * PR is the paper's (Section II.C, Eq. (9)-(12)): d1,2 = 1 +- sqrt2,
