@@ -76,6 +76,12 @@ def draw_kij(n, lo, hi, seed):
     return k + k.T
 
 
+def seeded_z(n, seed, concentration=20.0):
+    """Overall composition drawn around equimolar: Dirichlet(concentration * 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.dirichlet(np.full(n, concentration))
+
+
 def spinodal_z():
     """Overall composition of the ten-component n-alkane workload: the paper's
     Table VII composition with iC4+C4 and iC5+C5 merged and the CO2 and C7+

@@ -3,7 +3,7 @@ workload starts from, computed by the oracle's own flash / Maxwell code.
 
 Run: ``python -m oracle.write_phase_states`` (from the repository root);
 ``python -m oracle.write_phase_states <group>`` (a key of ``PARTIAL``:
-``droplet_c1c2c3``, ``ten_co2``, ``ternary_c1c2c3``, ``three_phase``)
+``vle_seeded``, ``droplet_c1c2c3``, ``ten_co2``, ``ternary_c1c2c3``, ``three_phase``)
 refreshes only that group of states.
 Only ``oracle/`` and the seeded draws in ``inputs/`` are used; nothing comes
 from the GPU path.  All densities stored are lattice-unit MASS densities per
@@ -205,7 +205,26 @@ def droplet_c1c2c3_state():
     return st
 
 
-PARTIAL = {"droplet_c1c2c3": lambda st: st.update(droplet_c1c2c3=droplet_c1c2c3_state()),
+def vle_seeded_states(seed=2):
+    """Table II cases 2-6 at their (T, p) with the overall composition drawn
+    around equimolar (Dirichlet(20 * 1), one draw per case from `seed`; a
+    draw that does not split is replaced by the next)."""
+    rng_seed = seed
+    out = {}
+    for case in range(2, 7):
+        comps, T, p = C.table_ii_components(case)
+        for k in range(100):
+            z = Fi.seeded_z(len(comps), rng_seed * 100 + case * 10 + k)
+            st = two_phase_state(comps, T, p, z)
+            if st is not None and 0.2 <= st["S_V"] <= 0.8:
+                break
+        st.update(components=comp_list(comps), T=T, z=list(z), draw=k)
+        out["vle%d_z2" % case] = st
+    return out
+
+
+PARTIAL = {"vle_seeded": lambda st: st.update(vle_seeded_states()),
+           "droplet_c1c2c3": lambda st: st.update(droplet_c1c2c3=droplet_c1c2c3_state()),
            "ten_co2": lambda st: st.update(ten_co2_states()),
            "ternary_c1c2c3": lambda st: st.update(ternary_c1c2c3=ternary_diagram_states()),
            "three_phase": lambda st: st.update(three_phase=three_phase_state())}
@@ -234,6 +253,7 @@ def main(only=None):
         st = two_phase_state(comps, T, p, z)
         st.update(components=comp_list(comps), T=T, z=z)
         states["vle%d" % case] = st
+    states.update(vle_seeded_states())
     # ten-component n-alkane spinodal: 325 K, 150 bar, seeded kij in [0, 0.05)
     kij = Fi.draw_kij(10, 0.0, 0.05, seed=4)
     z = Fi.spinodal_z()

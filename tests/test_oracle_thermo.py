@@ -412,7 +412,8 @@ def test_stored_two_phase_states_are_unstable_feeds():
     comp = lambda lst: [C.Component(**{k: c[k] for k in C.Component._fields}) for c in lst]
     checked = 0
     for key in ("droplet3", "vle2", "vle3", "vle4", "vle5", "vle6", "spinodal10",
-                "ten_co2_325", "ten_co2_400"):
+                "ten_co2_325", "ten_co2_400", "vle2_z2", "vle3_z2", "vle4_z2", "vle5_z2",
+                "vle6_z2"):
         st = S[key]
         cs = comp(st["components"])
         om = oracle_mixture(cs, st["T"], np.array(st["kij"]) if "kij" in st else None)
@@ -427,3 +428,23 @@ def test_stored_two_phase_states_are_unstable_feeds():
             assert not th.stability(om.pr, q["z"], om.units.p(q["p_bar_in"] * th.BAR)).stable
             checked += 1
     assert checked > 400
+
+
+def test_seeded_vle_states_follow_their_recipe():
+    """The seeded-composition Table II states: z is the stated draw
+    (Dirichlet(20 * 1) around equimolar, seed 2), the phases are the flash
+    at the case's (T, p) and that z, and z lies on their tie line."""
+    from inputs import fields as Fi
+    from oracle.lbm import oracle_mixture
+    S = Fi.load_phase_states()
+    for case in range(2, 7):
+        st = S["vle%d_z2" % case]
+        comps, T, p = C.table_ii_components(case)
+        z = Fi.seeded_z(len(comps), 2 * 100 + case * 10 + st["draw"])
+        np.testing.assert_allclose(st["z"], z, rtol=0, atol=0)
+        om = oracle_mixture(comps, T)
+        r = th.flash(om.pr, z, om.units.p(p * th.BAR))
+        np.testing.assert_allclose(st["x"], r.x, rtol=1e-12)
+        np.testing.assert_allclose(st["y"], r.y, rtol=1e-12)
+        np.testing.assert_allclose(r.beta * np.array(st["y"]) + (1 - r.beta) * np.array(st["x"]), z,
+                                   atol=1e-12)

@@ -48,9 +48,11 @@ def droplet64(noise=1e-3, seed=1, n=64, R=16.0):
     return Workload(C.DROPLET_3, 250.0, rho, (n, n))
 
 
-def vle(case, nx=256, ny=32, S_V=0.5):
-    """Flat-interface slab of Table II case `case` (C1..C6), liquid in the middle half."""
-    st = states()["vle%d" % case]
+def vle(case, nx=256, ny=32, S_V=0.5, seeded=False):
+    """Flat-interface slab of Table II case `case` (C1..C6), liquid in the
+    middle half; `seeded`: the overall composition drawn around equimolar
+    (cases 2-6) instead of equimolar."""
+    st = states()["vle%d_z2" % case if seeded else "vle%d" % case]
     comps, T, _ = C.table_ii_components(case)
     rho = Fi.slab(nx, ny, st["rho_V"], st["rho_L"], S_V)
     return Workload(comps, T, rho, (nx, ny))
