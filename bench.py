@@ -51,7 +51,7 @@ def build_inputs(n):
     return C.N_ALKANES, 325.0, np.array(st["kij"]), rho
 
 
-def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0, kernel=0):
+def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0, kernel=0, steady_steps=0):
     import torch
     from paper_2306_10652_amd import capi
     comps, T, kij, rho = build_inputs(n)
@@ -87,10 +87,21 @@ def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0, kernel=0):
     csu = N * n * n * steps / wall
     launch_s = kern_ms * 1e-3 / steps
     alg = info["alg_bytes_per_step"]
-    res = dict(csu=csu, wall=wall, ms_per_step=wall * 1e3 / steps, launch_ms=launch_s * 1e3,
-               alg_bytes=alg, achieved_gbs=alg / launch_s / 1e9, kernel=tuning["kernel"],
+    res = dict(csu=csu, csu_per_step=N * n * n, wall=wall, ms_per_step=wall * 1e3 / steps,
+               launch_ms=launch_s * 1e3, alg_bytes=alg, achieved_gbs=alg / launch_s / 1e9, kernel=tuning["kernel"],
                rows=tuning["rows"],
                status=d["status"], residual=d["residual"], mass=d["mass"].tolist())
+    if steady_steps:
+        # after the timed window: a longer run on the same simulation, for
+        # the rate once the GPU's clocks have settled under sustained load
+        ev0.record(stream)
+        sim.step_n(steady_steps)
+        ev1.record(stream)
+        ev1.synchronize()
+        ls = ev0.elapsed_time(ev1) * 1e-3 / steady_steps
+        res["steady"] = dict(steps=steady_steps, launch_ms=round(ls * 1e3, 5),
+                             value=round(N * n * n / ls, 1), achieved_gbs=round(alg / ls / 1e9, 1),
+                             frac=round(alg / ls / 1e9 / HBM_PEAK_GBS, 4))
     sim.close()
     return res
 
@@ -188,48 +199,65 @@ def time_vs_n_leg(steps=2000):
                 us_per_step_fp32_storage=[round(u, 2) for u in us32])
 
 
-def serving_leg(count=32, load=0.8, tol=1e-8, max_steps=60000, capacity_csu_s=None,
-                max_n2d=256, max_n3d=64):
-    """Continuous batching: Poisson arrivals of requests from the stored pool
-    (2-10 components; D2Q9 up to 256^2, D3Q19 up to 64^3 by default so the
-    leg stays within a minute; the `serving_full` leg keeps the pool's sizes,
-    up to 512^2 and 128^3), FP32 storage, run to residual tol.  The arrival
-    rate offers `load` x the measured batched throughput, using the mean work
-    of calibration requests served alone."""
+def serving_leg(count=10, load=0.8, tol=1e-8, max_steps=200000, max_n2d=None, max_n3d=None):
+    """Continuous batching over requests of the stored pool at their own
+    sizes (2-10 components; D2Q9 64^2 ... 512^2, D3Q19 64^3 ... 128^3): the
+    first `count` of the pool plus its first requests at the largest 2-D and
+    3-D sizes, FP32 storage, each run to residual tol or the step cap.  A first,
+    closed-loop pass (every request present at t = 0) measures each
+    request's work and the server's capacity; the timed pass then offers
+    `load` x that capacity with Poisson arrivals.  Time-to-equilibrium
+    percentiles are over the requests that converged; capped requests are
+    counted apart."""
     import torch
     from paper_2306_10652_amd import capi, serve
     from inputs import fields as Fi
     S = Fi.load_phase_states()["serving_pool"]
-    calib = serve.pool_requests(S, 4, rate_hz=1e6, tol=tol, max_steps=max_steps,
-                                max_n2d=max_n2d, max_n3d=max_n3d)
-    work = []
-    for r in calib:
+
+    def progress_fn(tag):
+        last = [0.0]
+
+        def progress(t, active, waiting, done):
+            if t - last[0] >= 15.0:
+                last[0] = t
+                print("serving %s: %.0f s, %d active, %d waiting, %d done"
+                      % (tag, t, active, waiting, done), file=sys.stderr, flush=True)
+        return progress
+
+    pool = S["requests"]
+    largest = []
+    for lat in ("D2Q9", "D3Q19"):
+        nmax = max(q["n"] for q in pool if q["lattice"] == lat)
+        largest.append(next(k for k, q in enumerate(pool) if q["lattice"] == lat and q["n"] == nmax))
+    idx = list(range(count)) + [k for k in largest if k >= count]
+    closed = serve.pool_requests(S, 0, rate_hz=1e9, tol=tol, max_steps=max_steps,
+                                 max_n2d=max_n2d, max_n3d=max_n3d, indices=idx)
+    for r in closed:
         r.arrival = 0.0
-        serve.Server(64 << 30).run([r])
-        work.append(r.csu())
+    t0 = time.perf_counter()
+    done0 = serve.Server(64 << 30, chunk=200).run(closed, progress=progress_fn("closed"))
+    wall0 = time.perf_counter() - t0
+    work = [r.csu() for r in done0 if r.status == 0]
+    capacity = sum(work) / wall0
     mean_work = float(np.mean(work))
-    cap = capacity_csu_s or 2.0e10
-    rate = load * cap / mean_work
-    reqs = serve.pool_requests(S, count, rate_hz=rate, tol=tol, max_steps=max_steps,
-                               max_n2d=max_n2d, max_n3d=max_n3d, seed=55)
+    rate = load * capacity / mean_work
+    reqs = serve.pool_requests(S, 0, rate_hz=rate, tol=tol, max_steps=max_steps,
+                               max_n2d=max_n2d, max_n3d=max_n3d, seed=55, indices=idx)
     srv = serve.Server(64 << 30, chunk=200)
     t0 = time.perf_counter()
-    last = [0.0]
-
-    def progress(t, active, waiting, done):
-        if t - last[0] >= 20.0:
-            last[0] = t
-            print("serving: %.0f s, %d active, %d waiting, %d done" % (t, active, waiting, done),
-                  file=sys.stderr, flush=True)
-    done = srv.run(reqs, progress=progress)
+    done = srv.run(reqs, progress=progress_fn("open"))
     wall = time.perf_counter() - t0
     st = serve.latency_stats(done)
     csu = sum(r.csu() for r in done if r.status == 0)
-    st.update(requests=count, max_n2d=max_n2d, max_n3d=max_n3d, offered_load=load,
-              arrival_rate_hz=round(rate, 3),
+    sizes = sorted(set((("D2Q9" if r.lattice == capi.D2Q9 else "D3Q19"), r.shape[0]) for r in reqs))
+    st.update(max_n2d=max(n for l, n in sizes if l == "D2Q9"),
+              max_n3d=max([n for l, n in sizes if l == "D3Q19"] or [0]),
+              d3q19_requests=sum(r.lattice != capi.D2Q9 for r in reqs),
+              offered_load=load, arrival_rate_hz=round(rate, 4),
+              closed_loop=dict(wall_s=round(wall0, 2), capacity_csu_s=round(capacity, 1),
+                               mean_work_csu=round(mean_work, 1)),
               hbm_budget_gb=64, tol=tol, max_steps=max_steps, wall_s=round(wall, 3),
-              throughput=dict(value=round(csu / wall, 1), unit="CSU/s"),
-              failed=int(sum(r.status != 0 for r in done)))
+              throughput=dict(value=round(csu / wall, 1), unit="CSU/s"))
     return st
 
 
@@ -323,6 +351,75 @@ def pmc_traffic(launch_alg_bytes):
     return pm.get("hbm_bytes_per_launch")
 
 
+def trace_summary(db_path, steps, steady=0):
+    """Per-kernel durations from a rocprofv3 results database (kernel-trace
+    run of this script): every dispatch, and the timed window of each
+    kernel, i.e. its `steps` dispatches before the last `steady` ones (for
+    the fused step kernels: after the autotuner's trial launches and the
+    warm-up, before the steady-state run).  Prints a markdown table."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    rows = list(db.execute("select name, start, end from kernels order by start"))
+    by = {}
+    for name, t0, t1 in rows:
+        by.setdefault(name, []).append((t1 - t0) / 1e3)
+    print("| kernel | calls | avg us (all) | timed window: calls | avg us | min us | max us |"
+          " steady: avg us |")
+    print("|---|---|---|---|---|---|---|---|")
+    for name, d in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        if steady and len(d) > steady + steps:
+            win, tail = d[len(d) - steady - steps:len(d) - steady], d[len(d) - steady:]
+        else:
+            win, tail = d[-steps:], []
+        short = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        print("| `%s` | %d | %.1f | %d | %.1f | %.1f | %.1f | %s |" % (
+            short, len(d), sum(d) / len(d), len(win), sum(win) / len(win), min(win), max(win),
+            "%.1f" % (sum(tail) / len(tail)) if tail else "-"))
+
+
+def _counter_values(db_path, counter):
+    """(kernel name, value) of every dispatch in a rocprofv3 counter-collection
+    database, in dispatch order."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    return [(n, v) for n, v in db.execute(
+        "select kernel_name, value from counters_collection where counter_name = ? "
+        "order by dispatch_id", (counter,))]
+
+
+def pmc_summary(out_path, fetch64, write64, fetch32, write32, calib_fetch, calib_write, steps,
+                copy_bytes=1 << 30):
+    """The HBM traffic summary of the fused kernel (profiles/ JSON read by
+    this script): FETCH_SIZE and WRITE_SIZE (KiB per dispatch, separate
+    counter runs of `--precision P --rows 74`) averaged over the last
+    `steps` dispatches of the fused kernel, each scaled by what the counter
+    reads for a plain device copy of `copy_bytes` (`--calib-copy-mib`)."""
+    def copy_kib(path, counter):
+        vals = [v for n, v in _counter_values(path, counter) if "copyBuffer" in n]
+        return max(vals)
+    f_fac = copy_bytes / (copy_kib(calib_fetch, "FETCH_SIZE") * 1024.0)
+    w_fac = copy_bytes / (copy_kib(calib_write, "WRITE_SIZE") * 1024.0)
+    per = {}
+    for prec, fpath, wpath, st in (("fp64", fetch64, write64, "double"),
+                                   ("fp32", fetch32, write32, "float")):
+        kern = KERNEL_NAMES[3] % st
+        fv = [v for n, v in _counter_values(fpath, "FETCH_SIZE") if kern in n.replace(" ", "")][-steps:]
+        wv = [v for n, v in _counter_values(wpath, "WRITE_SIZE") if kern in n.replace(" ", "")][-steps:]
+        rd = float(np.mean(fv)) * 1024.0 * f_fac
+        wr = float(np.mean(wv)) * 1024.0 * w_fac
+        alg = 2 * 10 * 1024 * 1024 * (8 + 8 * (8 if st == "double" else 4))
+        per[prec] = dict(kernel=kern, dispatches=len(fv), fetch_kib_raw=float(np.mean(fv)),
+                         write_kib_raw=float(np.mean(wv)), hbm_read_bytes_per_launch=rd,
+                         hbm_write_bytes_per_launch=wr, hbm_bytes_per_launch=rd + wr,
+                         alg_bytes_per_launch=alg, traffic_over_alg=(rd + wr) / alg)
+    out = dict(kernel_sha256_16=kernel_hash(), workload=WORKLOAD,
+               calibration=dict(copy_bytes=copy_bytes, fetch_factor=f_fac, write_factor=w_fac),
+               hbm_bytes_per_launch=per["fp64"]["hbm_bytes_per_launch"], per_precision=per)
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,13 +427,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--steady-steps", type=int, default=400,
+                    help="after the timed window, time this many more steps of the same "
+                         "simulation (reported as steady_state; 0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the sweep, time-vs-N and serving legs")
     ap.add_argument("--legs", default="sweep,time_vs_n,serving,d3q19",
                     help="comma-separated extra legs to run (sweep, time_vs_n, serving, "
-                         "d3q19; serving_full, the serving stream at the pool's own sizes, "
-                         "runs only when named)")
+                         "d3q19; serving_more, the serving stream over 32 requests, runs "
+                         "only when named)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
     ap.add_argument("--rows", type=int, default=0,
@@ -348,7 +448,23 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times "
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--trace-summary", default=None,
+                    help="only summarise a rocprofv3 results database of a kernel-trace run "
+                         "of this script (per-kernel durations; the last --steps dispatches "
+                         "of each kernel are the timed window)")
+    ap.add_argument("--pmc-summary", nargs=7, default=None,
+                    metavar=("OUT", "FETCH64", "WRITE64", "FETCH32", "WRITE32", "CALIB_FETCH",
+                             "CALIB_WRITE"),
+                    help="only write the HBM traffic summary OUT from rocprofv3 counter "
+                         "databases (FETCH_SIZE / WRITE_SIZE runs of --precision fp64 and fp32, "
+                         "and of --calib-copy-mib 1024); the last --steps dispatches are used")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, steps=args.steps)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.steps, args.steady_steps)
+        return
     if args.calib_copy_mib:
         import torch
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -373,8 +489,10 @@ def main():
         print(json.dumps(dict(precision=args.precision, **{k: v for k, v in r.items()
                                                              if k != "mass"})), flush=True)
         return
-    r64 = time_gpu(0, args.steps, args.warmup, args.n, rows=args.rows, kernel=args.kernel)
-    r32 = time_gpu(1, args.steps, args.warmup, args.n, rows=args.rows, kernel=args.kernel)
+    r64 = time_gpu(0, args.steps, args.warmup, args.n, rows=args.rows, kernel=args.kernel,
+                   steady_steps=args.steady_steps)
+    r32 = time_gpu(1, args.steps, args.warmup, args.n, rows=args.rows, kernel=args.kernel,
+                   steady_steps=args.steady_steps)
     traffic = pmc_traffic(r64["alg_bytes"])
     roof = dict(bound="hbm", achieved=round(r64["achieved_gbs"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4),
@@ -382,6 +500,8 @@ def main():
                 launch_ms=round(r64["launch_ms"], 5),
                 kernel=KERNEL_NAMES.get(r64["kernel"], "generic") % "double",
                 rows_per_item=r64["rows"])
+    if "steady" in r64:
+        roof["steady_state"] = r64["steady"]
     out = dict(metric="component-site updates/s & %HBM roofline; p50/p99 time-to-equilibrium",
                value=round(r64["csu"], 1),
                unit="CSU/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -396,8 +516,10 @@ def main():
                                  frac=round(r32["achieved_gbs"] / HBM_PEAK_GBS, 4),
                                  alg_bytes_per_launch=r32["alg_bytes"],
                                  launch_ms=round(r32["launch_ms"], 5),
+                                 frac_72B=round(72 * r32["csu_per_step"] / (r32["launch_ms"] * 1e-3)
+                                                / 1e9 / HBM_PEAK_GBS, 4),
                                  kernel=KERNEL_NAMES.get(r32["kernel"], "generic") % "float",
-                                 rows_per_item=r32["rows"]),
+                                 rows_per_item=r32["rows"], steady_state=r32.get("steady")),
                status=[r64["status"], r32["status"]])
     legs = set() if args.no_extra else set(args.legs.split(","))
     if "sweep" in legs:
@@ -405,13 +527,11 @@ def main():
     if "time_vs_n" in legs:
         out["time_vs_N"] = time_vs_n_leg()
     if "serving" in legs:
-        cap = out["batched_sweep"]["fp32_batched"]["value"] if "batched_sweep" in out else None
-        out["serving"] = serving_leg(capacity_csu_s=cap)
+        out["serving"] = serving_leg()
     if "d3q19" in legs:
         out["d3q19"] = d3q19_leg()
-    if "serving_full" in legs:
-        cap = out["batched_sweep"]["fp32_batched"]["value"] if "batched_sweep" in out else None
-        out["serving_full"] = serving_leg(capacity_csu_s=cap, max_n2d=None, max_n3d=None)
+    if "serving_more" in legs:
+        out["serving_more"] = serving_leg(count=30)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_budget)
     print(json.dumps(out), flush=True)

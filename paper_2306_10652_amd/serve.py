@@ -201,15 +201,18 @@ def latency_stats(done):
 
 
 def pool_requests(states, count, rate_hz, seed=5, precision=capi.FP32_STORAGE, tol=1e-8,
-                  max_steps=200000, max_n2d=None, max_n3d=None):
-    """Requests from the stored serving pool, Poisson arrivals at `rate_hz`."""
+                  max_steps=200000, max_n2d=None, max_n3d=None, indices=None):
+    """Requests from the stored serving pool (the first `count`, or the pool
+    entries `indices` in that order), Poisson arrivals at `rate_hz`."""
     from inputs import fields as Fi
     from .batch import _Comp
     comps_all = [_Comp(**c) for c in states["components"]]
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
     out = []
-    for k, q in enumerate(states["requests"][:count]):
+    pool = states["requests"]
+    picked = [(k, pool[k]) for k in indices] if indices is not None else list(enumerate(pool[:count]))
+    for k, q in picked:
         t += rng.exponential(1.0 / rate_hz)
         N = q["N"]
         n = q["n"]

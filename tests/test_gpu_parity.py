@@ -213,28 +213,33 @@ def test_tau_other_than_one(tau, lattice, shape, kernel):
     assert e <= 1e-10
 
 
-@pytest.mark.parametrize("case", [1, 2, 3, 4, 5, 6])
-def test_vle_cases_fp64(case):
-    """256 x 32 flat-interface slabs of Table II cases 1-6, 500 steps."""
-    wl = W.vle(case)
+VLE_CASES = [(c, False) for c in range(1, 7)] + [(c, True) for c in range(2, 7)]
+
+
+@pytest.mark.parametrize("case,seeded", VLE_CASES)
+def test_vle_cases_fp64(case, seeded):
+    """256 x 32 flat-interface slabs of Table II cases 1-6, equimolar and
+    (cases 2-6) with the seeded overall composition, 500 steps."""
+    wl = W.vle(case, seeded=seeded)
     o = wl.oracle()
     o.run(500)
     g = run_gpu(wl, 500)
     e = rel_err(g["rho"], o.rho())
-    report("vle", case=case, rho_rel=e)
+    report("vle", case=case, seeded=seeded, rho_rel=e)
     assert e <= 1e-10
 
 
-@pytest.mark.parametrize("case", [2, 6])
-def test_vle_fp32_storage(case):
-    """FP32 storage vs the FP64 oracle after 500 steps: every
-    density within the FP32-storage bar of 1e-4 relative."""
-    wl = W.vle(case)
+@pytest.mark.parametrize("case,seeded", VLE_CASES)
+def test_vle_fp32_storage(case, seeded):
+    """FP32 storage vs the FP64 oracle after 500 steps, every Table II case
+    (equimolar and seeded): every density within the FP32-storage bar of
+    1e-4 relative."""
+    wl = W.vle(case, seeded=seeded)
     o = wl.oracle()
     o.run(500)
     g = run_gpu(wl, 500, precision=1)
     e = rel_err(g["rho"], o.rho())
-    report("vle_fp32", case=case, rho_rel=e)
+    report("vle_fp32", case=case, seeded=seeded, rho_rel=e)
     assert e <= 1e-4
 
 

@@ -728,3 +728,45 @@ def test_d3q19_drop_fp32_storage_at_equilibrium():
     rel = [abs(a / b - 1) for a, b in zip(got[1], got[0])]
     report("d3q19_drop_fp32", rho_in=rel[0], rho_out=rel[1], dpRe=rel[2])
     assert max(rel) <= 1e-4
+
+
+def test_config2_vle_slabs_fp32_storage_against_fp64():
+    """The component-count sweep of Table II (cases 1-6, 256 x 32 slabs, liquid
+    in the middle half), equimolar and with the seeded overall composition
+    (cases 2-6), 20 000 steps in each precision, batched per precision and
+    component count: the bulk phases (16-column windows) of FP32 storage
+    against FP64 within 1e-4 relative in density and 1e-3 absolute in mole
+    fraction, the FP32-storage bar."""
+    capi = _capi()
+    n = 256
+    cases = [(c, False) for c in range(1, 7)] + [(c, True) for c in range(2, 7)]
+    runs = {}
+    for prec in (capi.FP64, capi.FP32_STORAGE):
+        sims = []
+        for case, seeded in cases:
+            wl = W.vle(case, seeded=seeded)
+            mix = wl.gpu_mixture()
+            s = capi.Simulation(mix, capi.D2Q9, prec, wl.shape, wl.rho)
+            s._mix = mix
+            sims.append(s)
+        capi.step_many(sims, 20000)
+        runs[prec] = sims
+    worst_rho = worst_x = 0.0
+    for k, (case, seeded) in enumerate(cases):
+        ph = []
+        for prec in (capi.FP64, capi.FP32_STORAGE):
+            s = runs[prec][k]
+            assert s.diagnostics()["rc"] == 0
+            M = s._mix.molar_masses_lu()
+            rt = s.read_moments(velocity=False)["rho"][:, 0] / M[:, None, None]
+            vap = np.concatenate([rt[:, :, 0:8], rt[:, :, n - 8:n]], axis=2).mean(axis=(1, 2))
+            liq = rt[:, :, n // 2 - 8:n // 2 + 8].mean(axis=(1, 2))
+            ph.append((vap, liq))
+        for (b64, b32) in zip(ph[0], ph[1]):
+            worst_rho = max(worst_rho, abs(float((b32 * M).sum() / (b64 * M).sum()) - 1))
+            worst_x = max(worst_x, float(np.max(np.abs(b32 / b32.sum() - b64 / b64.sum()))))
+        report("config2_fp32", case=case, seeded=seeded, rho_rel=worst_rho, x_abs=worst_x)
+    for prec in runs:
+        for s in runs[prec]:
+            s.close()
+    assert worst_rho <= 1e-4 and worst_x <= 1e-3
