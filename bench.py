@@ -199,11 +199,14 @@ def time_vs_n_leg(steps=2000):
                 us_per_step_fp32_storage=[round(u, 2) for u in us32])
 
 
-def serving_leg(count=10, load=0.8, tol=1e-8, max_steps=200000, max_n2d=None, max_n3d=None):
+def serving_leg(count=10, load=0.8, tol=1e-8, max_steps=200000, max_n2d=None, max_n3d=None,
+                largest=("D2Q9",)):
     """Continuous batching over requests of the stored pool at their own
     sizes (2-10 components; D2Q9 64^2 ... 512^2, D3Q19 64^3 ... 128^3): the
-    first `count` of the pool plus its first requests at the largest 2-D and
-    3-D sizes, FP32 storage, each run to residual tol or the step cap.  A first,
+    first `count` of the pool plus its first requests at the largest sizes
+    of the lattices in `largest` (the default leg leaves out the 128^3
+    D3Q19 request, whose ~9e4 steps take ~90 s alone), FP32 storage, each
+    run to residual tol or the step cap.  A first,
     closed-loop pass (every request present at t = 0) measures each
     request's work and the server's capacity; the timed pass then offers
     `load` x that capacity with Poisson arrivals.  Time-to-equilibrium
@@ -226,7 +229,7 @@ def serving_leg(count=10, load=0.8, tol=1e-8, max_steps=200000, max_n2d=None, ma
 
     pool = S["requests"]
     largest = []
-    for lat in ("D2Q9", "D3Q19"):
+    for lat in largest:
         nmax = max(q["n"] for q in pool if q["lattice"] == lat)
         largest.append(next(k for k, q in enumerate(pool) if q["lattice"] == lat and q["n"] == nmax))
     idx = list(range(count)) + [k for k in largest if k >= count]
@@ -296,6 +299,84 @@ def d3q19_leg(n=128, steps=100, warmup=10):
                          with_fields_gbs=round((pop + fields) / s / 1e9, 1),
                          status=sim.diagnostics()["status"])
         sim.close()
+    return out
+
+
+def small_configs_leg(config1_steps=2000, window=200, sweep_window=2):
+    """The CPU-baseline plan for the smaller configurations: the oracle
+    (all OpenMP threads and one thread) beside the GPU on
+    * the 64^2 C1/C3/nC5 droplet (config 1): its full 2000 steps on the
+      GPU (FP64, cache-resident: reported as steps/s and CSU/s), the
+      oracle over a `window`-step sample;
+    * the 256 x 32 Table II slabs, N = 1..6 (config 2): the oracle over a
+      `window`-step sample per case (the GPU side is the time-vs-N leg);
+    * the 256 ternary sweep instances (config 3): the oracle over
+      `sweep_window` steps of every instance, one after another.
+    Oracle rates are CSU/s over the stated samples."""
+    import torch
+    from paper_2306_10652_amd import capi
+    from inputs import components as C
+    from inputs import fields as Fi
+    from oracle.lbm import OracleLBM, oracle_mixture, build_oracle, set_threads
+    build_oracle()
+    S = Fi.load_phase_states()
+    threads = set_threads(0)
+    out = dict(cores=threads, cpu_model=cpu_model())
+    # config 1
+    st = S["droplet3"]
+    rho = Fi.add_noise(Fi.droplet(64, 64, st["rho_L"], st["rho_V"], 16.0), 1e-3, 1)
+    mix = capi.Mixture.from_components(C.DROPLET_3, 250.0)
+    stream = torch.cuda.Stream()
+    sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (64, 64), rho, stream=stream)
+    sim.step_n(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step_n(config1_steps)
+    torch.cuda.synchronize()
+    g = time.perf_counter() - t0
+    sim.close()
+    csu1 = 3 * 64 * 64
+    om = oracle_mixture(C.DROPLET_3, 250.0)
+    rates = {}
+    for nt in (threads, 1):
+        set_threads(nt)
+        o = OracleLBM(om, 0, (64, 64), rho)
+        t0 = time.perf_counter()
+        o.run(window)
+        rates[nt] = csu1 * window / (time.perf_counter() - t0)
+    out["config1_droplet64"] = dict(
+        gpu=dict(steps=config1_steps, steps_per_s=round(config1_steps / g, 1),
+                 csu_s=round(csu1 * config1_steps / g, 1)),
+        oracle=dict(sample="%d steps" % window, csu_s_all_cores=round(rates[threads], 1),
+                    csu_s_one_thread=round(rates[1], 1)))
+    # config 2
+    c2 = []
+    set_threads(threads)
+    for case in range(1, 7):
+        comps, T, _ = C.table_ii_components(case)
+        v = S["vle%d" % case]
+        o = OracleLBM(oracle_mixture(comps, T), 0, (256, 32),
+                      Fi.slab(256, 32, v["rho_V"], v["rho_L"], 0.5))
+        t0 = time.perf_counter()
+        o.run(window)
+        c2.append(round(len(comps) * 256 * 32 * window / (time.perf_counter() - t0), 1))
+    out["config2_vle_256x32"] = dict(N=[1, 2, 3, 4, 5, 6], oracle_csu_s_all_cores=c2,
+                                     sample="%d steps per case" % window)
+    # config 3
+    from paper_2306_10652_amd import batch
+    specs = batch.ternary_specs(S["ternary_sweep"])
+    csu = 0
+    el = 0.0
+    for sp in specs:
+        o = OracleLBM(oracle_mixture(sp["comps"], sp["T"]), 0, sp["shape"], sp["rho"])
+        t0 = time.perf_counter()
+        o.run(sweep_window)
+        el += time.perf_counter() - t0
+        csu += 3 * sp["shape"][0] * sp["shape"][1] * sweep_window
+        del o
+    out["config3_sweep"] = dict(instances=len(specs), oracle_csu_s_all_cores=round(csu / el, 1),
+                                sample="%d steps of each instance" % sweep_window)
+    set_threads(threads)
     return out
 
 
@@ -435,8 +516,9 @@ def main():
                     help="skip the sweep, time-vs-N and serving legs")
     ap.add_argument("--legs", default="sweep,time_vs_n,serving,d3q19",
                     help="comma-separated extra legs to run (sweep, time_vs_n, serving, "
-                         "d3q19; serving_more, the serving stream over 32 requests, runs "
-                         "only when named)")
+                         "d3q19; serving_more, the serving stream over more requests, and "
+                         "small_configs, the oracle on configurations 1-3 beside the GPU, "
+                         "run only when named)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
     ap.add_argument("--rows", type=int, default=0,
@@ -530,8 +612,10 @@ def main():
         out["serving"] = serving_leg()
     if "d3q19" in legs:
         out["d3q19"] = d3q19_leg()
+    if "small_configs" in legs:
+        out["small_configs"] = small_configs_leg()
     if "serving_more" in legs:
-        out["serving_more"] = serving_leg(count=30)
+        out["serving_more"] = serving_leg(count=20, largest=("D2Q9", "D3Q19"))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.n, args.cpu_budget)
     print(json.dumps(out), flush=True)
