@@ -31,10 +31,13 @@
  *    buffers swapped every step): row r holds the rest populations g_{0,i}
  *    of all components as [ncomp][nx] doubles, then the moving ones
  *    g_{a,i}, a >= 1, as [ncomp][Q-1][nx] values of the storage type
- *    (double, or float with FP32 storage).  With FP32 storage each step
- *    folds the rounding error of a site's moving populations into its rest
- *    population, so component masses are conserved to FP64 rounding.
- *    Arithmetic is FP64 in both precisions.  Host-side population arrays
+ *    (double, or float with FP32 storage).  With FP32 storage the fused
+ *    kernels collide the moving populations in FP32 arithmetic and store
+ *    the rest population as rho_i minus the FP64 sum of the stored moving
+ *    ones, so component masses are conserved to FP64 rounding; moments,
+ *    the EOS, psi_i and the gradients are FP64 in both precisions (the
+ *    multi-pass kernels keep the whole collision in FP64 and fold the
+ *    moving populations' rounding error into the rest population).  Host-side population arrays
  *    (read/write_populations) are [ncomp][Q][sites] FP64, site = x +
  *    nx*(y + ny*z).
  *  - Direction order a (lattice vector e_a):

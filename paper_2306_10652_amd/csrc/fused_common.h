@@ -79,6 +79,39 @@ __device__ __forceinline__ void collide_pair(double A, double B, double C9, doub
     tm = fma(eu, P - A, fma(-C3, eF, K));
 }
 
+// The same collision for FP32 storage: the eight moving populations in
+// FP32 arithmetic (they are stored in FP32; the per-site terms A, B, K, u,
+// F, G come in FP64 and are rounded once).  The caller stores the rest
+// population as rho - (the FP64 sum of the eight stored values, in
+// direction order), so that Eq. (1a)-(1c), which conserve each
+// component's mass, conserve it to FP64 rounding here too; the EOS, psi
+// and the gradients stay FP64.  m: direction a = m + 1 of the D2Q9 order.
+__device__ __forceinline__ double collide_moving_f32(double A, double B, double C9, double C3,
+                                                     double K1, double K2, double omc, double ux,
+                                                     double uy, double Fx, double Fy, double Gx,
+                                                     double Gy, const float (&g)[8],
+                                                     float (&t)[8]) {
+    const float fA = (float)A, fB = (float)B, f9 = (float)C9, f3 = (float)C3;
+    const float fomc = (float)omc;
+    const float fux = (float)ux, fuy = (float)uy, fFx = (float)Fx, fFy = (float)Fy;
+    const float fGx = (float)Gx, fGy = (float)Gy;
+    auto pair = [&](float K, float eu, float eF, float eG, float w, int mp, int mm) {
+        const float P = fmaf(f3, eG, fmaf(f9, eF, fB * eu));
+        const float tp = fmaf(eu, fA + P, fmaf(f3, eF, K));
+        const float tm = fmaf(eu, P - fA, fmaf(-f3, eF, K));
+        t[mp] = fmaf(fomc, g[mp], w * tp);
+        t[mm] = fmaf(fomc, g[mm], w * tm);
+    };
+    pair((float)K1, fux, fFx, fGx, 1.0f / 9.0f, 0, 2);
+    pair((float)K1, fuy, fFy, fGy, 1.0f / 9.0f, 1, 3);
+    pair((float)K2, fux + fuy, fFx + fFy, fGx + fGy, 1.0f / 36.0f, 4, 6);
+    pair((float)K2, fuy - fux, fFy - fFx, fGy - fGx, 1.0f / 36.0f, 5, 7);
+    double msum = 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) msum += (double)t[m];
+    return msum;
+}
+
 template <int NC>
 struct FusedLds {
     double rt[NC][64];      // molar densities of row r

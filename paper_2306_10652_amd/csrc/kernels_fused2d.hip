@@ -213,32 +213,44 @@ struct Fused {
             const uint32_t row0 = (uint32_t)wm2 * rsm;
             const uint32_t rowp = (uint32_t)wm1 * rsm;
             if (outl) {
-                // the four opposite pairs, stored as they are formed; then the
-                // rest population, which in FP32 storage also takes the
-                // rounding error of the eight moving ones (mass stays exact
-                // to FP64 rounding)
-                double err = 0.0;
-                auto put = [&](gmptr<ST> p, uint32_t at, double v) {
-                    const ST t = (ST)v;
-                    if (sizeof(ST) == 4) err += (double)t - v;
-                    p[at] = t;
-                };
-                double tp, tm;
-                collide_pair(A, B, C9, C3, K1, ux, Fx, Gx, tp, tm);
-                put(dst[0], row0 + xp, fma(omc, (double)gA.m[0], (1.0 / 9.0) * tp));
-                put(dst[2], row0 + xm, fma(omc, (double)gA.m[2], (1.0 / 9.0) * tm));
-                collide_pair(A, B, C9, C3, K1, uy, Fy, Gy, tp, tm);
-                put(dst[1], rowp + xc, fma(omc, (double)gA.m[1], (1.0 / 9.0) * tp));
-                put(dst[3], rowm + xc, fma(omc, (double)gA.m[3], (1.0 / 9.0) * tm));
-                collide_pair(A, B, C9, C3, K2, ux + uy, Fx + Fy, Gx + Gy, tp, tm);
-                put(dst[4], rowp + xp, fma(omc, (double)gA.m[4], (1.0 / 36.0) * tp));
-                put(dst[6], rowm + xm, fma(omc, (double)gA.m[6], (1.0 / 36.0) * tm));
-                collide_pair(A, B, C9, C3, K2, uy - ux, Fy - Fx, Gy - Gx, tp, tm);
-                put(dst[5], rowp + xm, fma(omc, (double)gA.m[5], (1.0 / 36.0) * tp));
-                put(dst[7], rowm + xp, fma(omc, (double)gA.m[7], (1.0 / 36.0) * tm));
-                const double g0 =
-                    fma(omc, gA.r, fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho));
-                dstR[(uint32_t)wm2 * rsr + (uint32_t)xc] = sizeof(ST) == 4 ? g0 - err : g0;
+                if constexpr (sizeof(ST) == 4) {
+                    // FP32 storage: the moving populations in FP32 arithmetic,
+                    // the rest population = rho - their stored sum (mass stays
+                    // exact to FP64 rounding)
+                    float g[8], t[8];
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) g[m] = (float)gA.m[m];
+                    const double msum = collide_moving_f32(A, B, C9, C3, K1, K2, omc, ux, uy, Fx,
+                                                           Fy, Gx, Gy, g, t);
+                    dst[0][row0 + xp] = t[0];
+                    dst[2][row0 + xm] = t[2];
+                    dst[1][rowp + xc] = t[1];
+                    dst[3][rowm + xc] = t[3];
+                    dst[4][rowp + xp] = t[4];
+                    dst[6][rowm + xm] = t[6];
+                    dst[5][rowp + xm] = t[5];
+                    dst[7][rowm + xp] = t[7];
+                    dstR[(uint32_t)wm2 * rsr + (uint32_t)xc] = rhm2 - msum;
+                } else {
+                    // the four opposite pairs, stored as they are formed; then
+                    // the rest population
+                    auto put = [&](gmptr<ST> p, uint32_t at, double v) { p[at] = (ST)v; };
+                    double tp, tm;
+                    collide_pair(A, B, C9, C3, K1, ux, Fx, Gx, tp, tm);
+                    put(dst[0], row0 + xp, fma(omc, (double)gA.m[0], (1.0 / 9.0) * tp));
+                    put(dst[2], row0 + xm, fma(omc, (double)gA.m[2], (1.0 / 9.0) * tm));
+                    collide_pair(A, B, C9, C3, K1, uy, Fy, Gy, tp, tm);
+                    put(dst[1], rowp + xc, fma(omc, (double)gA.m[1], (1.0 / 9.0) * tp));
+                    put(dst[3], rowm + xc, fma(omc, (double)gA.m[3], (1.0 / 9.0) * tm));
+                    collide_pair(A, B, C9, C3, K2, ux + uy, Fx + Fy, Gx + Gy, tp, tm);
+                    put(dst[4], rowp + xp, fma(omc, (double)gA.m[4], (1.0 / 36.0) * tp));
+                    put(dst[6], rowm + xm, fma(omc, (double)gA.m[6], (1.0 / 36.0) * tm));
+                    collide_pair(A, B, C9, C3, K2, uy - ux, Fy - Fx, Gy - Gx, tp, tm);
+                    put(dst[5], rowp + xm, fma(omc, (double)gA.m[5], (1.0 / 36.0) * tp));
+                    put(dst[7], rowm + xp, fma(omc, (double)gA.m[7], (1.0 / 36.0) * tm));
+                    dstR[(uint32_t)wm2 * rsr + (uint32_t)xc] =
+                        fma(omc, gA.r, fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho));
+                }
             }
         }
     }

@@ -153,8 +153,9 @@ struct Comp {
     }
 
     // ---- phase 3: velocity and collision of row y = r - 2 into the staging
-    // block (FP32 storage: the rest population takes the rounding error of
-    // the eight moving ones, so mass stays exact to FP64 rounding).
+    // block (FP32 storage: moving populations in FP32 arithmetic, the rest
+    // population = rho - their stored sum, so mass stays exact to FP64
+    // rounding).
     __device__ __forceinline__ void phase3(int r, const PopRow<ST> &gA, double rhm2, double Fx,
                                            double Fy, double Gx, double Gy) {
         double Fsx = 0.0, Fsy = 0.0;
@@ -175,12 +176,18 @@ struct Comp {
         const double Gu = Gx * ux + Gy * uy;
         const double K1 = fma(-0.5 * fcoef, Gu, base);
         const double K2 = fma(fcoef, Gu, base);
-        double err = 0.0;
-        auto put = [&](int a, double v) {
-            const ST t = (ST)v;
-            if (sizeof(ST) == 4) err += (double)t - v;
-            W.ogM[comp][a][lane] = t;
-        };
+        if constexpr (sizeof(ST) == 4) {
+            float g[8], t[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) g[m] = (float)gA.m[m];
+            const double msum = collide_moving_f32(A, B, C9, C3, K1, K2, omc, ux, uy, Fx, Fy, Gx,
+                                                   Gy, g, t);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) W.ogM[comp][m][lane] = (ST)t[m];
+            W.ogR[comp][lane] = rhm2 - msum;
+            return;
+        }
+        auto put = [&](int a, double v) { W.ogM[comp][a][lane] = (ST)v; };
         double tp, tm;
         collide_pair(A, B, C9, C3, K1, ux, Fx, Gx, tp, tm);
         put(0, fma(omc, (double)gA.m[0], (1.0 / 9.0) * tp));
@@ -194,8 +201,7 @@ struct Comp {
         collide_pair(A, B, C9, C3, K2, uy - ux, Fy - Fx, Gy - Gx, tp, tm);
         put(5, fma(omc, (double)gA.m[5], (1.0 / 36.0) * tp));
         put(7, fma(omc, (double)gA.m[7], (1.0 / 36.0) * tm));
-        const double g0 = fma(omc, gA.r, fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho));
-        W.ogR[comp][lane] = sizeof(ST) == 4 ? g0 - err : g0;
+        W.ogR[comp][lane] = fma(omc, gA.r, fma(4.0 / 9.0, fma(-2.0 * fcoef, Gu, base), orho));
     }
 
     // Row r-1 from the stash into gA (it is row r-2 of the next lead row),
