@@ -228,11 +228,11 @@ def serving_leg(count=10, load=0.8, tol=1e-8, max_steps=200000, max_n2d=None, ma
         return progress
 
     pool = S["requests"]
-    largest = []
+    extra = []
     for lat in largest:
         nmax = max(q["n"] for q in pool if q["lattice"] == lat)
-        largest.append(next(k for k, q in enumerate(pool) if q["lattice"] == lat and q["n"] == nmax))
-    idx = list(range(count)) + [k for k in largest if k >= count]
+        extra.append(next(k for k, q in enumerate(pool) if q["lattice"] == lat and q["n"] == nmax))
+    idx = list(range(count)) + [k for k in extra if k >= count]
     closed = serve.pool_requests(S, 0, rate_hz=1e9, tol=tol, max_steps=max_steps,
                                  max_n2d=max_n2d, max_n3d=max_n3d, indices=idx)
     for r in closed:
@@ -448,11 +448,13 @@ def trace_summary(db_path, steps, steady=0):
           " steady: avg us |")
     print("|---|---|---|---|---|---|---|---|")
     for name, d in sorted(by.items(), key=lambda kv: -sum(kv[1])):
-        if steady and len(d) > steady + steps:
-            win, tail = d[len(d) - steady - steps:len(d) - steady], d[len(d) - steady:]
-        else:
-            win, tail = d[-steps:], []
         short = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        if len(d) <= steady + steps:
+            # not a step kernel of the timed loop (trial launches, read-outs)
+            print("| `%s` | %d | %.1f | | | | | |" % (short, len(d), sum(d) / len(d)))
+            continue
+        win = d[len(d) - steady - steps:len(d) - steady]
+        tail = d[len(d) - steady:] if steady else []
         print("| `%s` | %d | %.1f | %d | %.1f | %.1f | %.1f | %s |" % (
             short, len(d), sum(d) / len(d), len(win), sum(win) / len(win), min(win), max(win),
             "%.1f" % (sum(tail) / len(tail)) if tail else "-"))
