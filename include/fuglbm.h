@@ -27,17 +27,21 @@
  *    never keeps a caller's host pointer.
  *  - A mixture must outlive every simulation made from it.  Handles are not
  *    thread-safe: use one handle from one thread at a time.
- *  - Device populations are blocked by lattice row (row = y + ny*z, two
- *    buffers swapped every step): row r holds the rest populations g_{0,i}
- *    of all components as [ncomp][nx] doubles, then the moving ones
- *    g_{a,i}, a >= 1, as [ncomp][Q-1][nx] values of the storage type
- *    (double, or float with FP32 storage).  With FP32 storage the fused
- *    kernels collide the moving populations in FP32 arithmetic and store
- *    the rest population as rho_i minus the FP64 sum of the stored moving
- *    ones, so component masses are conserved to FP64 rounding; moments,
- *    the EOS, psi_i and the gradients are FP64 in both precisions (the
- *    multi-pass kernels keep the whole collision in FP64 and fold the
- *    moving populations' rounding error into the rest population).  Host-side population arrays
+ *  - Device populations (two buffers swapped every step): with FP64
+ *    storage they are blocked by lattice row (row = y + ny*z): row r holds
+ *    the rest populations g_{0,i} of all components as [ncomp][pitch]
+ *    doubles, then the moving ones g_{a,i}, a >= 1, as [ncomp][Q-1][pitch]
+ *    doubles.  With FP32 storage every (component, direction) has one
+ *    array over the whole grid: [ncomp][sites + pad] doubles (rest), then
+ *    [ncomp][Q-1][sites + pad] floats (moving).  With FP32 storage the
+ *    rest population is stored as rho_i minus the FP64 sum of the site's
+ *    stored moving populations, so component masses are conserved to FP64
+ *    rounding (Eq. (1a)-(1c) conserve each component's mass); the fused
+ *    D2Q9 kernels collide the moving populations in FP32 arithmetic, the
+ *    multi-pass kernels in FP64 (at tau != 1 the multi-pass
+ *    collision instead folds the moving populations' rounding error into
+ *    the rest population).  Moments, the EOS, psi_i and the gradients are
+ *    FP64 in both precisions.  Host-side population arrays
  *    (read/write_populations) are [ncomp][Q][sites] FP64, site = x +
  *    nx*(y + ny*z).
  *  - Direction order a (lattice vector e_a):
@@ -219,7 +223,12 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int6
 
 /* Launch tuning: kernel 0 = automatic, 1 = four-pass generic kernels,
  * 2 = fused one-pass D2Q9 kernel (register ring), 3 = fused one-pass D2Q9
- * kernel with store wavefronts (ncomp <= 10; bit-identical results);
+ * kernel with store wavefronts (ncomp <= 10; bit-identical results),
+ * 4 = three-pass D3Q19 step (moments; velocity, with psi_i formed in
+ * LDS; collision and push of every component of a tile in one workgroup,
+ * the next component's loads in flight; bit-identical to kernel 1).
+ * Automatic: the fused kernels for D2Q9 (1 beyond 2^32 buffer elements),
+ * 4 for D3Q19;
  * rows = output rows per fused work item (>= 1, fixed), or 0 = autotuned:
  * the next fuglbm_step_n times a few trial launches per candidate (they
  * read the current state and write the spare buffer, so the state does
@@ -232,7 +241,7 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int6
  * use, or rows < 0. */
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *sim, int32_t kernel, int32_t rows);
 
-/* Query the launch tuning in use: kernel (1 generic, 2 or 3 fused) and
+/* Query the launch tuning in use: kernel (1 four-pass, 2 or 3 fused, 4 three-pass) and
  * fused rows per work item (0 for the generic kernels; with autotuning,
  * the values chosen once a step has run). */
 fuglbm_status fuglbm_get_tuning(const fuglbm_sim *sim, int32_t *kernel, int32_t *rows);

@@ -228,6 +228,20 @@ static bool fused_fits(const fuglbm_sim *s) {
     return s->lattice == FUGLBM_D2Q9 && elems < ((int64_t)1 << 32);
 }
 
+// Launch variants: 1 = four-pass generic kernels, 2 / 3 = fused one-pass
+// D2Q9 kernels (register ring / store wavefronts), 4 = three-pass D3Q19
+// step (moments; velocity; collision and push of every component of a
+// tile in one workgroup).
+static bool is_fused(int kernel) { return kernel == 2 || kernel == 3; }
+
+static bool three_pass_fits(const fuglbm_sim *s) { return s->lattice == FUGLBM_D3Q19; }
+
+// The variant a simulation starts with (and kernel 0 of set_tuning picks).
+static int default_kernel(const fuglbm_sim *s) {
+    if (fused_fits(s)) return default_fused(s->N, s->fp32);
+    return three_pass_fits(s) ? 4 : 1;
+}
+
 static uint64_t next_sim_uid() {
     static uint64_t n = 0;
     return ++n;
@@ -280,9 +294,13 @@ void drop_graph(fuglbm_sim *s) {
 }
 
 hipError_t launch_one_step(fuglbm_sim *s, int flip_parity, hipStream_t st) {
-    if (s->kernel >= 2)
+    if (is_fused(s->kernel))
         return launch_fused(s->kernel, s->N, s->fp32, s->items, s->nitems, s->fsim, flip_parity,
                             st);
+    if (s->kernel == 4)
+        return launch_step_three_pass(s->fp32, s->dc, s->nx, s->ny, s->nz, s->buf[flip_parity],
+                                      s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
+                                      s->u_f, s->status, s->hc.omega != 1.0, st);
     return launch_step_generic(s->lattice, s->fp32, s->dc, s->N, s->nx, s->ny, s->nz, s->buf[flip_parity],
                                s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
                                s->u_f, s->status, s->hc.omega != 1.0, st);
@@ -707,7 +725,7 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     e = hipMemcpy(s->fsim, &fs, sizeof(FusedSim), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(hip_fail(e, "upload fused sim"));
     const bool fused = fused_fits(s);
-    s->kernel = fused ? default_fused(N, s->fp32) : 1;
+    s->kernel = default_kernel(s);
     s->rows = fused ? auto_rows(nx, ny, N, s->fp32, s->kernel) : 0;
     s->auto_kernel = fused;
     if (fused) {
@@ -728,22 +746,24 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
 fuglbm_status fuglbm_get_tuning(const fuglbm_sim *s, int32_t *kernel, int32_t *rows) {
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
     if (kernel) *kernel = s->kernel;
-    if (rows) *rows = s->kernel >= 2 ? s->rows : 0;
+    if (rows) *rows = is_fused(s->kernel) ? s->rows : 0;
     return FUGLBM_OK;
 }
 
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
-    if (kernel < 0 || kernel > 3) return fail(FUGLBM_EINVAL, "kernel must be 0, 1, 2 or 3");
-    if (kernel >= 2 && !fused_fits(s))
+    if (kernel < 0 || kernel > 4) return fail(FUGLBM_EINVAL, "kernel must be 0, 1, 2, 3 or 4");
+    if (is_fused(kernel) && !fused_fits(s))
         return fail(FUGLBM_EINVAL, "the fused kernel is D2Q9 only, with < 2^32 elements per buffer");
+    if (kernel == 4 && !three_pass_fits(s))
+        return fail(FUGLBM_EINVAL, "the three-pass step is D3Q19 only");
     if (kernel == 3 && !ws_usable(s->N, s->fp32))
         return fail(FUGLBM_EINVAL, "the store-wave fused kernel is built for at most 10 components");
     if (rows < 0) return fail(FUGLBM_EINVAL, "rows must be >= 0");
-    const int k = kernel == 0 ? (fused_fits(s) ? default_fused(s->N, s->fp32) : 1) : kernel;
-    s->auto_kernel = kernel == 0 && k >= 2;
+    const int k = kernel == 0 ? default_kernel(s) : kernel;
+    s->auto_kernel = kernel == 0 && is_fused(k);
     int r = s->rows;
-    if (k >= 2) {
+    if (is_fused(k)) {
         r = rows == 0 ? auto_rows(s->nx, s->ny, s->N, s->fp32, k) : std::min<int>(rows, s->ny);
         s->autotune = rows == 0;
         s->tuned = false;
@@ -778,7 +798,7 @@ fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
     hipStream_t st = (hipStream_t)hip_stream;
     s->last_stream = st;
     int64_t left = nsteps;
-    if (left > 0 && s->kernel >= 2 && s->autotune && !s->tuned) {
+    if (left > 0 && is_fused(s->kernel) && s->autotune && !s->tuned) {
         fuglbm_status rc = autotune_rows(s, st);
         if (rc != FUGLBM_OK) return rc;
     }
@@ -871,7 +891,13 @@ fuglbm_status fuglbm_diagnostics(fuglbm_sim *s, fuglbm_diag *diag) {
 }
 
 extern "C++" {
-// Host copy of one buffer <-> [N][Q][sites] FP64 (the layout is PopLayout).
+// Column of the stored moving population a of column x (pop_col).
+static int host_pop_col(const fuglbm_sim *s, int a, int x) {
+    return s->lattice == FUGLBM_D3Q19 ? pop_col<D3Q19>(a, x, s->nx) : pop_col<D2Q9>(a, x, s->nx);
+}
+
+// Host copy of one buffer <-> [N][Q][sites] FP64 (the layout is PopLayout,
+// the moving populations' columns pop_col).
 template <typename ST>
 void unpack_pops(const fuglbm_sim *s, const char *buf, double *g) {
     const PopLayout<ST> P(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz);
@@ -885,7 +911,7 @@ void unpack_pops(const fuglbm_sim *s, const char *buf, double *g) {
                     for (int x = 0; x < s->nx; ++x) o[x] = src[x];
                 } else {
                     const ST *src = (const ST *)(buf + P.move(r, i, a, 0));
-                    for (int x = 0; x < s->nx; ++x) o[x] = (double)src[x];
+                    for (int x = 0; x < s->nx; ++x) o[x] = (double)src[host_pop_col(s, a, x)];
                 }
             }
 }
@@ -903,7 +929,7 @@ void pack_pops(const fuglbm_sim *s, const double *g, char *buf) {
                     for (int x = 0; x < s->nx; ++x) dst[x] = in[x];
                 } else {
                     ST *dst = (ST *)(buf + P.move(r, i, a, 0));
-                    for (int x = 0; x < s->nx; ++x) dst[x] = (ST)in[x];
+                    for (int x = 0; x < s->nx; ++x) dst[host_pop_col(s, a, x)] = (ST)in[x];
                 }
             }
 }
@@ -952,10 +978,10 @@ fuglbm_status fuglbm_poke_population(fuglbm_sim *s, int32_t comp, int32_t a, int
         HIP_TRY(hipMemcpy(b + off, &value, 8, hipMemcpyHostToDevice));
     } else if (s->fp32) {
         const float f = (float)value;
-        const int64_t off = PopLayout<float>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).move(row, comp, a, x);
+        const int64_t off = PopLayout<float>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).move(row, comp, a, host_pop_col(s, a, x));
         HIP_TRY(hipMemcpy(b + off, &f, 4, hipMemcpyHostToDevice));
     } else {
-        const int64_t off = PopLayout<double>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).move(row, comp, a, x);
+        const int64_t off = PopLayout<double>(s->N, s->Q, s->nx, (int64_t)s->ny * s->nz).move(row, comp, a, host_pop_col(s, a, x));
         HIP_TRY(hipMemcpy(b + off, &value, 8, hipMemcpyHostToDevice));
     }
     return FUGLBM_OK;
@@ -1179,7 +1205,7 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             skipped = true;
             continue;
         }
-        if (s->lattice == FUGLBM_D2Q9 && s->kernel >= 2)
+        if (s->lattice == FUGLBM_D2Q9 && is_fused(s->kernel))
             groups[{s->N, s->fp32 ? 1 : 0}].push_back(s);
         else
             others.push_back(s);
@@ -1361,7 +1387,7 @@ extern "C" fuglbm_status fuglbm_step_many_noalloc(fuglbm_sim *const *sims, int32
         if (!s) return fail(FUGLBM_EINVAL, "null sim in batch");
         for (int q = 0; q < k; ++q)
             if (sims[q] == s) return fail(FUGLBM_EINVAL, "duplicate sim in batch");
-        if (s->lattice != FUGLBM_D2Q9 || s->kernel < 2)
+        if (s->lattice != FUGLBM_D2Q9 || !is_fused(s->kernel))
             return fail(FUGLBM_EINVAL, "only D2Q9 simulations on a fused kernel");
         if (s->rows < 1) return fail(FUGLBM_EINVAL, "simulation without fused rows");
         cls[k] = -1;

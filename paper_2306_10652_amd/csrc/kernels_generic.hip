@@ -7,11 +7,10 @@
 // One thread per site; fields between passes live in the simulation's
 // workspace.  Also: initial populations, the macroscopic read-out and the
 // per-block diagnostic partial sums.
-#include "kernels.h"
+#include "generic_tiles.h"
 
 namespace {
 
-constexpr int TPB = 256;
 
 template <class L>
 __device__ __forceinline__ int64_t nb_site(int x, int y, int z, int a, int nx, int ny, int nz) {
@@ -20,33 +19,6 @@ __device__ __forceinline__ int64_t nb_site(int x, int y, int z, int a, int nx, i
     yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
     return (int64_t)xx + (int64_t)nx * ((int64_t)yy + (int64_t)ny * zz);
-}
-
-// Lattice gradient in pairwise-difference form; phi(site) read through f.
-template <class L, class Fn>
-__device__ __forceinline__ void lattice_grad(const int64_t *nb, Fn f, double &gx, double &gy,
-                                             double &gz) {
-    gx = gy = gz = 0.0;
-#pragma unroll
-    for (int a = 1; a < L::Q; ++a) {
-        // visit each opposite pair once: the member with the first non-zero
-        // component positive
-        const int fx = L::ex(a), fy = L::ey(a), fz = L::ez(a);
-        const bool first = fx > 0 || (fx == 0 && (fy > 0 || (fy == 0 && fz > 0)));
-        if (!first) continue;
-        int o = 0;
-#pragma unroll
-        for (int b = 1; b < L::Q; ++b)
-            if (L::ex(b) == -fx && L::ey(b) == -fy && L::ez(b) == -fz) o = b;
-        const double d = f(nb[a]) - f(nb[o]);
-        const double wd = L::w(a) * d;
-        gx += fx * wd;
-        gy += fy * wd;
-        gz += fz * wd;
-    }
-    gx *= 3.0;
-    gy *= 3.0;
-    gz *= 3.0;
 }
 
 template <class L, typename ST>
@@ -94,7 +66,7 @@ __global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict_
             double r = 0.0;
 #pragma unroll
             for (int a = 0; a < L::Q; ++a) {
-                const double v = ld_pop<ST>(g, P, row, i, a, xs);
+                const double v = ld_pop<ST>(g, P, row, i, a, a == 0 ? xs : pop_col<L>(a, xs, nx));
                 r += v;
                 jx += L::ex(a) * v;
                 jy += L::ey(a) * v;
@@ -154,47 +126,17 @@ __global__ __launch_bounds__(TPB) void k_interface(const SimConst *__restrict__ 
     double acc = 0.0;
 #pragma unroll
     for (int a = 1; a < L::Q; ++a)
-        acc += L::w(a) * (s_f[nb_site<L>(x, y, z, a, nx, ny, nz)] - sc);
+        acc = fma(L::w(a), s_f[nb_site<L>(x, y, z, a, nx, ny, nz)] - sc, acc);
     const double lap = 6.0 * acc;
     const int N = c->N;
-    for (int i = 0; i < N; ++i) psi_f[(int64_t)i * ns + s] -= c->sqk[i] * lap;
+    // explicit fused operations here and in the velocity pass: the three-pass
+    // kernel evaluates the same expressions and must round them the same way
+    for (int i = 0; i < N; ++i) {
+        const int64_t k = (int64_t)i * ns + s;
+        psi_f[k] = fma(-c->sqk[i], lap, psi_f[k]);
+    }
 }
 
-// ---- LDS-tiled force, velocity and collision --------------------------------
-// A workgroup owns a tile of TX x TY x TZ sites (one thread per site) and
-// stages psi_i (and rho_i) over the tile plus a one-site halo in LDS, so
-// every neighbour value is read from HBM/L2 once per tile instead of once
-// per neighbour.
-//
-// Collision tiles are 64 sites wide: a wavefront covers 64 consecutive x
-// sites of one row, so each of its population stores is one 512 B (FP64) /
-// 256 B (FP32) run.  The velocity pass only reads, and takes the shape with
-// the smallest halo.
-//
-// Tiles are numbered x-fastest (collision units: collide_unit), and each
-// XCD takes a contiguous range of work units
-// (workgroups go to the XCDs round-robin).  The units that write a lattice
-// row's blocks and the partly written cache lines at tile edges then run
-// at the same time on the same L2, and the pages being written at any
-// moment are few.
-template <class L> struct TileC;
-template <> struct TileC<D2Q9> { static constexpr int TX = 64, TY = 4, TZ = 1, HZ = 0; };
-template <> struct TileC<D3Q19> { static constexpr int TX = 64, TY = 2, TZ = 2, HZ = 1; };
-template <class L> struct TileV;
-template <> struct TileV<D2Q9> { static constexpr int TX = 64, TY = 4, TZ = 1, HZ = 0; };
-template <> struct TileV<D3Q19> { static constexpr int TX = 16, TY = 4, TZ = 4, HZ = 1; };
-constexpr int TILE_XCDS = 8;
-
-// This workgroup's work unit; gridDim.x is a multiple of TILE_XCDS
-// (unit_blocks), units at or past the real count are padding.
-__device__ __forceinline__ int xcd_unit() {
-    const int per = (int)gridDim.x / TILE_XCDS;
-    return (int)(blockIdx.x % TILE_XCDS) * per + (int)(blockIdx.x / TILE_XCDS);
-}
-
-inline unsigned unit_blocks(int64_t units) {
-    return (unsigned)((units + TILE_XCDS - 1) / TILE_XCDS * TILE_XCDS);
-}
 
 // Collision work unit -> (tile, component).  Units go through the tiles in
 // chunks of COLLIDE_CHUNK, each chunk component by component, so the
@@ -209,106 +151,6 @@ __device__ __forceinline__ void collide_unit(int unit, int ntiles, int N, int &t
     tile = t0 + r % kk;
 }
 
-template <class L, class S>
-struct TileGeom {
-    static constexpr int TX = S::TX, TY = S::TY, TZ = S::TZ, HZ = S::HZ;
-    static constexpr int HX = TX + 2, HY = TY + 2, HZN = TZ + 2 * HZ;
-    static constexpr int NH = HX * HY * HZN;   // halo tile points
-    static_assert(TX * TY * TZ == TPB, "one thread per tile site");
-    int x0, y0, z0, lx, ly, lz, x, y, z;
-    bool active;
-    int lc;      // LDS index of this thread's site
-    __host__ __device__ static int64_t count(int nx, int ny, int nz) {
-        return (int64_t)((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + TZ - 1) / TZ);
-    }
-    // tile b < count(nx, ny, nz), numbered x-fastest
-    __device__ TileGeom(const SimConst *c, int b) {
-        const int ntx = (c->nx + TX - 1) / TX, nty = (c->ny + TY - 1) / TY;
-        x0 = (b % ntx) * TX;
-        y0 = ((b / ntx) % nty) * TY;
-        z0 = (b / (ntx * nty)) * TZ;
-        const int t = threadIdx.x;
-        lx = t % TX;
-        ly = (t / TX) % TY;
-        lz = t / (TX * TY);
-        x = x0 + lx;
-        y = y0 + ly;
-        z = z0 + lz;
-        active = x < c->nx && y < c->ny && z < c->nz;
-        lc = ((lz + HZ) * HY + (ly + 1)) * HX + (lx + 1);
-    }
-    __device__ static int lds_off(int a) { return (L::ez(a) * HY + L::ey(a)) * HX + L::ex(a); }
-    // periodic image of v >= -1 (a tile can be wider than the grid)
-    __device__ static int wrap(int v, int n) {
-        v = v < 0 ? v + n : v;
-        while (v >= n) v -= n;
-        return v;
-    }
-    // stage field f (one component plane of ns values) into lds[NH]; each
-    // thread issues all of its loads before its first LDS write, so the
-    // loads are in flight together
-    __device__ void stage(const SimConst *c, const double *f, double *lds) const {
-        const int nx = c->nx, ny = c->ny, nz = c->nz;
-        if constexpr (TX == 64) {
-            // a wavefront stages whole halo rows (HX = 66 x sites): one
-            // y/z wrap per row, one wrapped x per lane for all rows
-            constexpr int NW = TPB / 64;
-            const int lane = threadIdx.x & 63;
-            const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-            const int gx0 = wrap(x0 - 1 + lane, nx);
-            const int gx1 = wrap(x0 + 63 + (lane & 1), nx);   // halo x = 64, 65
-            constexpr int NR = (HY * HZN + NW - 1) / NW;   // rows per wavefront
-            double v0[NR], v1[NR];
-#pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const int row = wv + j * NW;
-                if (row < HY * HZN) {
-                    const int hy = row % HY, hz = row / HY;
-                    const int gy = wrap(y0 - 1 + hy, ny), gz = wrap(z0 - HZ + hz, nz);
-                    const double *fr = f + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz);
-                    v0[j] = fr[gx0];
-                    v1[j] = fr[gx1];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const int row = wv + j * NW;
-                if (row < HY * HZN) {
-                    lds[row * HX + lane] = v0[j];
-                    if (lane < 2) lds[row * HX + 64 + lane] = v1[j];
-                }
-            }
-        } else {
-            // NK halo points per thread
-            constexpr int NK = (NH + TPB - 1) / TPB;
-            double v[NK];
-#pragma unroll
-            for (int j = 0; j < NK; ++j) {
-                const int k = (int)threadIdx.x + j * TPB;
-                if (k < NH) {
-                    const int hx = k % HX, hy = (k / HX) % HY, hz = k / (HX * HY);
-                    const int gx = wrap(x0 - 1 + hx, nx), gy = wrap(y0 - 1 + hy, ny),
-                              gz = wrap(z0 - HZ + hz, nz);
-                    v[j] = f[(int64_t)gx + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz)];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < NK; ++j) {
-                const int k = (int)threadIdx.x + j * TPB;
-                if (k < NH) lds[k] = v[j];
-            }
-        }
-    }
-    __device__ void grad(const double *lds, double &gx, double &gy, double &gz) const {
-        int nb[L::Q];
-#pragma unroll
-        for (int a = 0; a < L::Q; ++a) nb[a] = lc + lds_off(a);
-        int64_t nb64[L::Q];
-#pragma unroll
-        for (int a = 0; a < L::Q; ++a) nb64[a] = nb[a];
-        lattice_grad<L>(nb64, [&](int64_t t) { return lds[t]; }, gx, gy, gz);
-    }
-};
 
 // u = (j + F/2) / rho, F = sum_i F_i, F_i = -rt_i grad psi_i  -> u_f
 template <class L>
@@ -335,16 +177,16 @@ __global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__
             T.grad(lp, gx, gy, gz);
             const double r = rho_f[(int64_t)i * ns + s];
             const double rt = r * c->invM[i];
-            Fx -= rt * gx;
-            Fy -= rt * gy;
-            Fz -= rt * gz;
+            Fx = fma(-rt, gx, Fx);
+            Fy = fma(-rt, gy, Fy);
+            Fz = fma(-rt, gz, Fz);
             rhot += r;
         }
     }
     if (!T.active) return;
-    u_f[s] = (j_f[s] + 0.5 * Fx) / rhot;
-    u_f[ns + s] = (j_f[ns + s] + 0.5 * Fy) / rhot;
-    if (L::D == 3) u_f[2 * ns + s] = (j_f[2 * ns + s] + 0.5 * Fz) / rhot;
+    u_f[s] = fma(0.5, Fx, j_f[s]) / rhot;
+    u_f[ns + s] = fma(0.5, Fy, j_f[ns + s]) / rhot;
+    if (L::D == 3) u_f[2 * ns + s] = fma(0.5, Fz, j_f[2 * ns + s]) / rhot;
 }
 
 // collision (Eq. (1a)-(1c)) and push of one component over one tile
@@ -371,14 +213,12 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
     const int nx = c->nx, ny = c->ny, nz = c->nz;
     const int64_t s = T.active ? (int64_t)T.x + (int64_t)nx * ((int64_t)T.y + (int64_t)ny * T.z) : 0;
     const PopLayout<ST> P(N, L::Q, nx, (int64_t)ny * nz);
-    const int64_t row = (int64_t)T.y + (int64_t)ny * T.z;
     double ux = 0.0, uy = 0.0, uz = 0.0;
     if (T.active) {
         ux = u_f[s];
         uy = u_f[ns + s];
         uz = (L::D == 3) ? u_f[2 * ns + s] : 0.0;
     }
-    const double uu = ux * ux + uy * uy + uz * uz;
     const double omega = c->omega, fcoef = c->fcoef;
     const char *gsb = (const char *)gs;
     char *gdb = (char *)gd;
@@ -393,68 +233,12 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
         const double r = lr[T.lc];
         const double rt = r * c->invM[i];
         const double Fx = -rt * gx, Fy = -rt * gy, Fz = -rt * gz;
-        const double Fu = Fx * ux + Fy * uy + Fz * uz;
-        const double Gu = Gx * ux + Gy * uy + Gz * uz;
-        // moving populations first; in FP32 storage their rounding error
-        // goes into the rest population, which stays at this site.  At
-        // tau = 1 the collision does not depend on the old populations
-        // (their moments came from the first pass): they are not read.
-        double err = 0.0;
-        // tau = 1: collide_one for a moving direction with the site's terms
-        // taken out of the direction loop: g^eq_a - w_a rho = w_a rho sq_a and
-        // F_a / w_a = 3 eF + 9 eu eF + 3 eu eG + K, where K depends on |e_a|^2
-        // only (weight classes |e|^2 = 1 and 2); the dot products with e_a
-        // add only its non-zero components (0 * u is not folded away)
-        const double c0 = -1.5 * uu;
-        const double K1 = -3.0 * Fu - Gu + 0.5 * (3.0 - (double)L::D) * Gu;
-        const double K2 = -3.0 * Fu - Gu + 0.5 * (6.0 - (double)L::D) * Gu;
-        const double A1 = omega * L::w(1) * r, A2 = omega * L::w(L::Q - 1) * r;
-        const double B1 = fcoef * L::w(1), B2 = fcoef * L::w(L::Q - 1);
-        auto edot = [](int a, double x, double y, double z) {
-            const int cx = L::ex(a), cy = L::ey(a), cz = L::ez(a);
-            const double tx = cx > 0 ? x : -x, ty = cy > 0 ? y : -y, tz = cz > 0 ? z : -z;
-            if (cx != 0) return cy != 0 ? tx + ty : (cz != 0 ? tx + tz : tx);
-            return cy != 0 ? (cz != 0 ? ty + tz : ty) : tz;
-        };
-        auto dir = [&](int a) {
-            double o;
-            if constexpr (KEEP) {
-                const double gv = (double)*(const ST *)(gsb + P.move(row, i, a, T.x));
-                o = collide_one<L>(a, gv, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
-                                   omega, fcoef);
-            } else {
-                const double eu = edot(a, ux, uy, uz);
-                const double eF = edot(a, Fx, Fy, Fz);
-                const double eG = edot(a, Gx, Gy, Gz);
-                const bool e1 = L::ex(a) * L::ex(a) + L::ey(a) * L::ey(a) +
-                                L::ez(a) * L::ez(a) == 1;
-                const double sq = fma(eu, fma(4.5, eu, 3.0), c0);
-                const double q = fma(eF, fma(9.0, eu, 3.0), fma(3.0 * eu, eG, e1 ? K1 : K2));
-                o = fma(e1 ? A1 : A2, sq, (e1 ? B1 : B2) * q);
-            }
-            const ST v = (ST)o;
-            if (sizeof(ST) == 4) err += (double)v - o;
-            int xx = T.x + L::ex(a), yy = T.y + L::ey(a), zz = T.z + L::ez(a);
-            xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-            yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
-            zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-            *(ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)) = v;
-        };
-        if constexpr (KEEP) {
-            // rolled: unrolled, the compiler hoists every load and the
-            // kernel needs 256 registers (one wavefront per SIMD)
-#pragma unroll 2
-            for (int a = 1; a < L::Q; ++a) dir(a);
-        } else {
-            // no loads: unrolled, the lattice vectors, weights and
-            // destination rows fold to constants per direction
-#pragma unroll
-            for (int a = 1; a < L::Q; ++a) dir(a);
-        }
-        const double g0 = KEEP ? *(const double *)(gsb + P.rest(row, i, T.x)) : 0.0;
-        const double o0 = collide_one<L>(0, g0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
-                                         omega, fcoef);
-        *(double *)(gdb + P.rest(row, i, T.x)) = sizeof(ST) == 4 ? o0 - err : o0;
+        if constexpr (KEEP)
+            collide_push_keep<L, ST>(P, gsb, gdb, i, T.x, T.y, T.z, nx, ny, nz, r, ux, uy, uz, Fx,
+                                     Fy, Fz, Gx, Gy, Gz, omega, fcoef);
+        else
+            collide_push_tau1<L, ST>(P, gdb, i, T.x, T.y, T.z, nx, ny, nz, r, ux, uy, uz, Fx, Fy,
+                                     Fz, Gx, Gy, Gz, omega, fcoef);
     }
 }
 
@@ -624,6 +408,23 @@ hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int nc
                     : step_generic_t<D2Q9, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
     return fp32 ? step_generic_t<D3Q19, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st)
                 : step_generic_t<D3Q19, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
+}
+
+hipError_t launch_step_three_pass(bool fp32, const SimConst *c, int nx, int ny, int nz,
+                                  const void *gs, void *gd, double *rho_f, double *psi_f,
+                                  double *s_f, double *j_f, double *u_f, uint32_t *status,
+                                  bool keep_old, hipStream_t st) {
+    const unsigned nb = nblocks((int64_t)nx * ny * nz);
+    if (fp32)
+        hipLaunchKernelGGL((k_moments_eos<D3Q19, float>), dim3(nb), dim3(TPB), 0, st, c, gs, rho_f,
+                           psi_f, s_f, j_f, status);
+    else
+        hipLaunchKernelGGL((k_moments_eos<D3Q19, double>), dim3(nb), dim3(TPB), 0, st, c, gs, rho_f,
+                           psi_f, s_f, j_f, status);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_velocity_collide(fp32, c, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f,
+                                   keep_old, st);
 }
 
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int nx, int ny, int nz,

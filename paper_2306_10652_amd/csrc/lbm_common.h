@@ -42,6 +42,7 @@ struct SimConst {
 struct D2Q9 {
     static constexpr int Q = 9;
     static constexpr int D = 2;
+    static constexpr bool PULL_X = false;   // see pop_col
     __host__ __device__ static constexpr int ex(int a) {
         return a == 1 || a == 5 || a == 8 ? 1 : (a == 3 || a == 6 || a == 7 ? -1 : 0);
     }
@@ -57,6 +58,7 @@ struct D2Q9 {
 struct D3Q19 {
     static constexpr int Q = 19;
     static constexpr int D = 3;
+    static constexpr bool PULL_X = true;    // see pop_col
     // faces: 1 +x, 2 -x, 3 +y, 4 -y, 5 +z, 6 -z
     // edges: 7 (+x+y) 8 (-x-y) 9 (+x-y) 10 (-x+y) 11 (+x+z) 12 (-x-z)
     //        13 (+x-z) 14 (-x+z) 15 (+y+z) 16 (-y-z) 17 (+y-z) 18 (-y+z)
@@ -156,8 +158,10 @@ __device__ __forceinline__ double collide_one(int a, double g, double rho, doubl
 // Population storage of one buffer.  The rest populations are FP64 in both
 // precisions; the moving ones (a >= 1) are stored as ST (double for FP64,
 // float for FP32 storage).  In FP32 storage a kernel that writes a site
-// folds the rounding error of the site's moving populations into its rest
-// population, so every component's mass is conserved to FP64 rounding.
+// stores its rest population as rho minus the FP64 sum of the stored moving
+// ones (the collision at tau != 1 of the multi-pass path folds their
+// rounding error into it instead), so every component's mass is conserved
+// to FP64 rounding.  Moving populations sit at the columns pop_col gives.
 //
 // FP64: blocked by lattice row (row = y + ny*z).  Row `row` is one
 // contiguous block [N][pitch] double (rest) ++ [N][Q-1][pitch] double
@@ -208,6 +212,21 @@ struct PopLayout<float> {
     __host__ __device__ int64_t move_row_stride() const { return nx; }
     __host__ __device__ int64_t bytes(int64_t /*rows*/) const { return move_base + move_base / 2 * Qm; }
 };
+
+// Column of the stored moving population a (a >= 1) that belongs to column
+// x of a row.  D3Q19 keeps each moving population at the column it was
+// collided at and moves it along y and z only (push in y and z, pull in
+// x): population a of column x sits at column x - e_x(a) of x's row, so a
+// collision's stores are whole aligned rows (a 64-wide store shifted by
+// one column straddles five cache lines, two of them partly written).
+// D2Q9 keeps every population at its own site (the fused D2Q9 kernels
+// push in x as well).
+template <class L>
+__host__ __device__ inline int pop_col(int a, int x, int nx) {
+    if (!L::PULL_X) return x;
+    const int v = x - L::ex(a);
+    return v < 0 ? v + nx : (v >= nx ? v - nx : v);
+}
 
 template <typename ST>
 __device__ __forceinline__ double ld_pop(const void *buf, const PopLayout<ST> &L, int64_t row,
