@@ -267,11 +267,10 @@ def serving_leg(count=10, load=0.8, tol=1e-8, max_steps=200000, max_n2d=None, ma
 def d3q19_leg(n=128, steps=100, warmup=10):
     """The largest D3Q19 request of the serving stream: the ten-component
     spinodal mixture on a n^3 periodic grid (uniform, +-1 % noise), FP64
-    and FP32 storage, on the three-pass step the library picks (kernel 4)
-    and on the four-pass step (kernel 1).  Kernel time from HIP events on
-    the library's stream; traffic per step both as the populations alone
-    (the headline's definition) and with the fields the passes exchange
-    (three-pass: 6N + 15 values per site; four-pass: 8N + 14)."""
+    and FP32 storage, multi-pass path.  Kernel time from HIP events on the
+    library's stream; traffic per step both as the populations alone (the
+    headline's definition) and with the fields the passes exchange
+    (8N + 14 values per site)."""
     import torch
     from paper_2306_10652_amd import capi
     from inputs import components as C
@@ -284,29 +283,24 @@ def d3q19_leg(n=128, steps=100, warmup=10):
     stream = torch.cuda.Stream()
     out = dict(grid=[n, n, n], components=N, lattice="D3Q19", steps=steps)
     for prec, name in ((capi.FP64, "fp64"), (capi.FP32_STORAGE, "fp32_storage")):
-        for kernel, suffix, fvals in ((0, "", 6 * N + 15), (1, "_four_pass", 8 * N + 14)):
-            sim = capi.Simulation(mix, capi.D3Q19, prec, (n, n, n), rho, stream=stream)
-            if kernel:
-                sim.set_tuning(kernel, 0)
-            sim.step_n(warmup)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            sim.step_n(steps)
-            e1.record(stream)
-            e1.synchronize()
-            s = e0.elapsed_time(e1) * 1e-3 / steps
-            pop = sim.info()["alg_bytes_per_step"]
-            fields = fvals * 8 * ns
-            out[name + suffix] = dict(
-                kernel=sim.get_tuning()["kernel"], ms_per_step=round(s * 1e3, 4),
-                value=round(N * ns / s, 1), unit="CSU/s",
-                populations_gbs=round(pop / s / 1e9, 1),
-                populations_frac=round(pop / s / 1e9 / HBM_PEAK_GBS, 4),
-                with_fields_gbs=round((pop + fields) / s / 1e9, 1),
-                status=sim.diagnostics()["status"])
-            sim.close()
+        sim = capi.Simulation(mix, capi.D3Q19, prec, (n, n, n), rho, stream=stream)
+        sim.step_n(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step_n(steps)
+        e1.record(stream)
+        e1.synchronize()
+        s = e0.elapsed_time(e1) * 1e-3 / steps
+        pop = sim.info()["alg_bytes_per_step"]
+        fields = (8 * N + 14) * 8 * ns
+        out[name] = dict(ms_per_step=round(s * 1e3, 4), value=round(N * ns / s, 1), unit="CSU/s",
+                         populations_gbs=round(pop / s / 1e9, 1),
+                         populations_frac=round(pop / s / 1e9 / HBM_PEAK_GBS, 4),
+                         with_fields_gbs=round((pop + fields) / s / 1e9, 1),
+                         status=sim.diagnostics()["status"])
+        sim.close()
     return out
 
 

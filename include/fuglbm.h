@@ -223,12 +223,9 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int6
 
 /* Launch tuning: kernel 0 = automatic, 1 = four-pass generic kernels,
  * 2 = fused one-pass D2Q9 kernel (register ring), 3 = fused one-pass D2Q9
- * kernel with store wavefronts (ncomp <= 10; bit-identical results),
- * 4 = three-pass D3Q19 step (moments; velocity, with psi_i formed in
- * LDS; collision and push of every component of a tile in one workgroup,
- * the next component's loads in flight; bit-identical to kernel 1).
+ * kernel with store wavefronts (ncomp <= 10; bit-identical results).
  * Automatic: the fused kernels for D2Q9 (1 beyond 2^32 buffer elements),
- * 4 for D3Q19;
+ * 1 for D3Q19;
  * rows = output rows per fused work item (>= 1, fixed), or 0 = autotuned:
  * the next fuglbm_step_n times a few trial launches per candidate (they
  * read the current state and write the spare buffer, so the state does
@@ -241,7 +238,7 @@ fuglbm_status fuglbm_write_populations(fuglbm_sim *sim, const double *g_in, int6
  * use, or rows < 0. */
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *sim, int32_t kernel, int32_t rows);
 
-/* Query the launch tuning in use: kernel (1 four-pass, 2 or 3 fused, 4 three-pass) and
+/* Query the launch tuning in use: kernel (1 generic, 2 or 3 fused) and
  * fused rows per work item (0 for the generic kernels; with autotuning,
  * the values chosen once a step has run). */
 fuglbm_status fuglbm_get_tuning(const fuglbm_sim *sim, int32_t *kernel, int32_t *rows);

@@ -16,8 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfuglbm.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels_generic.hip", "kernels_force_collide.hip", "kernels_fused2d.hip",
-           "kernels_fused2d_ws.hip",
+SOURCES = ["kernels_generic.hip", "kernels_fused2d.hip", "kernels_fused2d_ws.hip",
            "fuglbm_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

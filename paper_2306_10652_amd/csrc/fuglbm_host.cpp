@@ -229,17 +229,12 @@ static bool fused_fits(const fuglbm_sim *s) {
 }
 
 // Launch variants: 1 = four-pass generic kernels, 2 / 3 = fused one-pass
-// D2Q9 kernels (register ring / store wavefronts), 4 = three-pass D3Q19
-// step (moments; velocity; collision and push of every component of a
-// tile in one workgroup).
+// D2Q9 kernels (register ring / store wavefronts).
 static bool is_fused(int kernel) { return kernel == 2 || kernel == 3; }
-
-static bool three_pass_fits(const fuglbm_sim *s) { return s->lattice == FUGLBM_D3Q19; }
 
 // The variant a simulation starts with (and kernel 0 of set_tuning picks).
 static int default_kernel(const fuglbm_sim *s) {
-    if (fused_fits(s)) return default_fused(s->N, s->fp32);
-    return three_pass_fits(s) ? 4 : 1;
+    return fused_fits(s) ? default_fused(s->N, s->fp32) : 1;
 }
 
 static uint64_t next_sim_uid() {
@@ -297,10 +292,6 @@ hipError_t launch_one_step(fuglbm_sim *s, int flip_parity, hipStream_t st) {
     if (is_fused(s->kernel))
         return launch_fused(s->kernel, s->N, s->fp32, s->items, s->nitems, s->fsim, flip_parity,
                             st);
-    if (s->kernel == 4)
-        return launch_step_three_pass(s->fp32, s->dc, s->nx, s->ny, s->nz, s->buf[flip_parity],
-                                      s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
-                                      s->u_f, s->status, s->hc.omega != 1.0, st);
     return launch_step_generic(s->lattice, s->fp32, s->dc, s->N, s->nx, s->ny, s->nz, s->buf[flip_parity],
                                s->buf[flip_parity ^ 1], s->rho_f, s->psi_f, s->s_f, s->j_f,
                                s->u_f, s->status, s->hc.omega != 1.0, st);
@@ -752,11 +743,9 @@ fuglbm_status fuglbm_get_tuning(const fuglbm_sim *s, int32_t *kernel, int32_t *r
 
 fuglbm_status fuglbm_set_tuning(fuglbm_sim *s, int32_t kernel, int32_t rows) {
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
-    if (kernel < 0 || kernel > 4) return fail(FUGLBM_EINVAL, "kernel must be 0, 1, 2, 3 or 4");
+    if (kernel < 0 || kernel > 3) return fail(FUGLBM_EINVAL, "kernel must be 0, 1, 2 or 3");
     if (is_fused(kernel) && !fused_fits(s))
         return fail(FUGLBM_EINVAL, "the fused kernel is D2Q9 only, with < 2^32 elements per buffer");
-    if (kernel == 4 && !three_pass_fits(s))
-        return fail(FUGLBM_EINVAL, "the three-pass step is D3Q19 only");
     if (kernel == 3 && !ws_usable(s->N, s->fp32))
         return fail(FUGLBM_EINVAL, "the store-wave fused kernel is built for at most 10 components");
     if (rows < 0) return fail(FUGLBM_EINVAL, "rows must be >= 0");

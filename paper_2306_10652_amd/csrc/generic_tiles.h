@@ -1,7 +1,7 @@
-// LDS-tiled stencil machinery shared by the multi-pass kernels and the
-// three-pass D3Q19 step: the workgroup size, the lattice
-// gradient, tile shapes, XCD-aware work-unit numbering and the tile
-// geometry with its halo staging.
+// LDS-tiled stencil machinery of the multi-pass kernels: the workgroup
+// size, the lattice gradient, tile shapes, XCD-aware work-unit numbering,
+// the tile geometry with its halo staging, and the collision-and-push of
+// one component at one site.
 #pragma once
 
 #include "kernels.h"
@@ -164,98 +164,6 @@ struct TileGeom {
             }
         }
     }
-    // The same tile with a two-site halo (the interface term's Laplacian at
-    // the one-site halo points): HX2 x HY2 x HZ2N points.
-    static constexpr int HX2 = TX + 4, HY2 = TY + 4, HZ2N = TZ + 4 * HZ;
-    static constexpr int NH2 = HX2 * HY2 * HZ2N;
-    // periodic image of v >= -2
-    __device__ static int wrap2(int v, int n) {
-        while (v < 0) v += n;
-        while (v >= n) v -= n;
-        return v;
-    }
-    // stage field f into lds2[NH2] (two-site halo; 64-wide tiles)
-    __device__ void stage2(const SimConst *c, const double *f, double *lds2) const {
-        static_assert(TX == 64, "row staging needs 64-wide tiles");
-        const int nx = c->nx, ny = c->ny, nz = c->nz;
-        constexpr int NW = TPB / 64;
-        const int lane = threadIdx.x & 63;
-        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int gx0 = wrap2(x0 - 2 + lane, nx);
-        const int gx1 = wrap2(x0 + 62 + (lane & 3), nx);   // halo x = 64 .. 67
-        constexpr int NR = (HY2 * HZ2N + NW - 1) / NW;
-        double v0[NR], v1[NR];
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const int row = wv + j * NW;
-            if (row < HY2 * HZ2N) {
-                const int hy = row % HY2, hz = row / HY2;
-                const int gy = wrap2(y0 - 2 + hy, ny), gz = wrap2(z0 - 2 * HZ + hz, nz);
-                const double *fr = f + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz);
-                v0[j] = fr[gx0];
-                v1[j] = fr[gx1];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const int row = wv + j * NW;
-            if (row < HY2 * HZ2N) {
-                lds2[row * HX2 + lane] = v0[j];
-                if (lane < 4) lds2[row * HX2 + 64 + lane] = v1[j];
-            }
-        }
-    }
-    // index in the two-site-halo grid of one-site-halo point k < NH
-    __device__ static int halo2_index(int k) {
-        const int hx = k % HX, hy = (k / HX) % HY, hz = k / (HX * HY);
-        return ((hz + HZ) * HY2 + (hy + 1)) * HX2 + (hx + 1);
-    }
-    __device__ static int lds2_off(int a) {
-        return (L::ez(a) * HY2 + L::ey(a)) * HX2 + L::ex(a);
-    }
-    // One-site-halo staging split into its loads (into registers) and its
-    // LDS writes, so that the loads of the next field can be in flight while
-    // the current one is used (64-wide tiles).
-    static constexpr int NR1 = (HY * HZN + TPB / 64 - 1) / (TPB / 64);
-    struct HaloRegs {
-        double v0[NR1], v1[NR1];
-    };
-    __device__ void load_halo(const SimConst *c, const double *f, HaloRegs &h) const {
-        static_assert(TX == 64, "row staging needs 64-wide tiles");
-        const int nx = c->nx, ny = c->ny, nz = c->nz;
-        constexpr int NW = TPB / 64;
-        const int lane = threadIdx.x & 63;
-        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int gx0 = wrap(x0 - 1 + lane, nx);
-        const int gx1 = wrap(x0 + 63 + (lane & 1), nx);
-#pragma unroll
-        for (int j = 0; j < NR1; ++j) {
-            const int row = wv + j * NW;
-            if (row < HY * HZN) {
-                const int hy = row % HY, hz = row / HY;
-                const int gy = wrap(y0 - 1 + hy, ny), gz = wrap(z0 - HZ + hz, nz);
-                const double *fr = f + (int64_t)nx * ((int64_t)gy + (int64_t)ny * gz);
-                h.v0[j] = fr[gx0];
-                h.v1[j] = fr[gx1];
-            }
-        }
-    }
-    // lds[k] = fn(k, loaded value) for every halo point k this thread loaded
-    template <class Fn>
-    __device__ void put_halo(const HaloRegs &h, double *lds, Fn fn) const {
-        constexpr int NW = TPB / 64;
-        const int lane = threadIdx.x & 63;
-        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-#pragma unroll
-        for (int j = 0; j < NR1; ++j) {
-            const int row = wv + j * NW;
-            if (row < HY * HZN) {
-                const int k0 = row * HX + lane;
-                lds[k0] = fn(k0, h.v0[j]);
-                if (lane < 2) lds[row * HX + 64 + lane] = fn(row * HX + 64 + lane, h.v1[j]);
-            }
-        }
-    }
     __device__ void grad(const double *lds, double &gx, double &gy, double &gz) const {
         int nb[L::Q];
 #pragma unroll
@@ -289,8 +197,8 @@ __device__ __forceinline__ void collide_push_tau1(const PopLayout<ST> &P, char *
                                                   double Gz, double omega, double fcoef) {
     // the inputs as plain register values (empty register constraints, no
     // instruction): otherwise a caller that has just computed F_i as a
-    // product lets the compiler fuse that product into e_a.F, and the same
-    // collision would round differently in different kernels
+    // product lets the compiler fuse that product into e_a.F, and the
+    // rounding would depend on the caller
     asm volatile("" : "+v"(r), "+v"(ux), "+v"(uy), "+v"(uz), "+v"(Fx), "+v"(Fy), "+v"(Fz),
                  "+v"(Gx), "+v"(Gy), "+v"(Gz));
     const double uu = ux * ux + uy * uy + uz * uz;

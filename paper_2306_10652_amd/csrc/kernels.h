@@ -29,18 +29,6 @@ hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int nc
                                int nz, const void *gs, void *gd, double *rho_f, double *psi_f,
                                double *s_f, double *j_f, double *u_f, uint32_t *status,
                                bool keep_old, hipStream_t st);
-// Three-pass D3Q19 step: the moments pass (rho_i, RT ln f_i -> psi_f, s,
-// j), the velocity pass (psi_i formed in LDS, u -> u_f), then the
-// collision and push of every component of a tile in one workgroup.  Same
-// bits as the four-pass step.
-hipError_t launch_step_three_pass(bool fp32, const SimConst *c, int nx, int ny, int nz,
-                                  const void *gs, void *gd, double *rho_f, double *psi_f,
-                                  double *s_f, double *j_f, double *u_f, uint32_t *status,
-                                  bool keep_old, hipStream_t st);
-hipError_t launch_velocity_collide(bool fp32, const SimConst *c, int nx, int ny, int nz,
-                                   const void *gs, void *gd, const double *rho_f,
-                                   const double *mu_f, const double *s_f, const double *j_f,
-                                   double *u_f, bool keep_old, hipStream_t st);
 // Macroscopic fields of a state: rho_i, RT ln f_i -> psi_i, s, j and (u_f
 // non-null) the force-corrected velocity.
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int nx, int ny, int nz,

@@ -129,8 +129,8 @@ __global__ __launch_bounds__(TPB) void k_interface(const SimConst *__restrict__ 
         acc = fma(L::w(a), s_f[nb_site<L>(x, y, z, a, nx, ny, nz)] - sc, acc);
     const double lap = 6.0 * acc;
     const int N = c->N;
-    // explicit fused operations here and in the velocity pass: the three-pass
-    // kernel evaluates the same expressions and must round them the same way
+    // explicit fused operations (here and in the velocity pass), so that
+    // the rounding does not depend on the compiler's contraction choices
     for (int i = 0; i < N; ++i) {
         const int64_t k = (int64_t)i * ns + s;
         psi_f[k] = fma(-c->sqk[i], lap, psi_f[k]);
@@ -408,23 +408,6 @@ hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int nc
                     : step_generic_t<D2Q9, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
     return fp32 ? step_generic_t<D3Q19, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st)
                 : step_generic_t<D3Q19, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
-}
-
-hipError_t launch_step_three_pass(bool fp32, const SimConst *c, int nx, int ny, int nz,
-                                  const void *gs, void *gd, double *rho_f, double *psi_f,
-                                  double *s_f, double *j_f, double *u_f, uint32_t *status,
-                                  bool keep_old, hipStream_t st) {
-    const unsigned nb = nblocks((int64_t)nx * ny * nz);
-    if (fp32)
-        hipLaunchKernelGGL((k_moments_eos<D3Q19, float>), dim3(nb), dim3(TPB), 0, st, c, gs, rho_f,
-                           psi_f, s_f, j_f, status);
-    else
-        hipLaunchKernelGGL((k_moments_eos<D3Q19, double>), dim3(nb), dim3(TPB), 0, st, c, gs, rho_f,
-                           psi_f, s_f, j_f, status);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_velocity_collide(fp32, c, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f,
-                                   keep_old, st);
 }
 
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int nx, int ny, int nz,

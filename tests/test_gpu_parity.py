@@ -134,26 +134,23 @@ def test_ragged_grids_fp32_storage_fused(N, kernel):
         assert err <= 1e-6 and e <= 1e-6
 
 
-@pytest.mark.parametrize("kernel", [1, 4])
 @pytest.mark.parametrize("shape,N,tau", [((70, 6, 5), 7, 1.0), ((130, 3, 9), 3, 1.0),
                                          ((5, 5, 5), 1, 1.0), ((64, 2, 64), 10, 1.0),
                                          ((33, 65, 6), 2, 1.0), ((70, 6, 5), 7, 1.3),
                                          ((129, 4, 3), 16, 1.0)])
-def test_d3q19_ragged_grids(shape, N, tau, kernel):
-    """D3Q19 on grids that cut the tiles raggedly: wider than one 64-site
-    tile but not a multiple of it, thin in y or z (the halos, one and two
-    sites deep, wrap onto the grid itself), tile counts that leave a
+def test_d3q19_ragged_grids(shape, N, tau):
+    """D3Q19 multi-pass path on grids that cut its tiles raggedly: wider
+    than one 64-site collision tile but not a multiple of it, thin in y or
+    z (the halo wraps onto the grid itself), tile counts that leave a
     partial last chunk of collision units, N = 1..16, and tau != 1 (the
-    rolled collision); the four-pass path (kernel 1) and the three-pass path
-    (kernel 4).  Populations and densities after 1 and 7 steps."""
+    rolled collision).  Populations (stored pushed in y and z, pulled in x)
+    and densities after 1 and 7 steps."""
     wl = W.random_droplet(N, shape, seed=N * 10 + shape[0], lattice=1)
     wl.tau = tau
     o = wl.oracle()
     capi = _capi()
     mix = wl.gpu_mixture()
     sim = capi.Simulation(mix, 1, 0, shape, wl.rho)
-    sim.set_tuning(kernel, 0)
-    assert sim.get_tuning()["kernel"] == kernel
     for steps in (1, 6):
         assert o.run(steps) == 0
         sim.step_n(steps)
@@ -161,57 +158,8 @@ def test_d3q19_ragged_grids(shape, N, tau, kernel):
         go = oracle_populations(o, 1)
         err = float(np.max(np.abs(gg - go)) / np.max(np.abs(go)))
         e = rel_err(sim.read_moments(velocity=False)["rho"], o.rho())
-        report("d3q19_ragged", shape=shape, N=N, tau=tau, kernel=kernel, steps=o.steps, pop=err,
-               rho=e)
+        report("d3q19_ragged", shape=shape, N=N, tau=tau, steps=o.steps, pop=err, rho=e)
         assert err <= 1e-12 and e <= 1e-12
-
-
-@pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("N,tau", [(n, 1.0) for n in range(1, 11)] + [(16, 1.0), (4, 1.3), (9, 0.8)])
-def test_d3q19_three_pass_bitwise_four_pass(N, tau, precision):
-    """The three-pass D3Q19 step (kernel 4) gives the four-pass step's bits
-    (kernel 1): every site's arithmetic is the same, term for term, in both
-    precisions, at tau = 1 and otherwise.  A 67 x 5 x 7 grid (a partial
-    64-wide tile, odd y and z against the 2 x 2 tile), N = 1..10 and 16,
-    five steps from a noisy drop."""
-    capi = _capi()
-    shape = (67, 5, 7)
-    wl = W.random_droplet(N, shape, seed=70 + N, lattice=1)
-    wl.tau = tau
-    mix = wl.gpu_mixture()
-    out = []
-    for kernel in (1, 4):
-        sim = capi.Simulation(mix, 1, precision, shape, wl.rho)
-        sim.set_tuning(kernel, 0)
-        sim.step_n(5)
-        out.append(sim.read_populations())
-        assert sim.read_moments(velocity=False)["status"] == 0
-        sim.close()
-    report("d3q19_three_pass_bitwise", N=N, tau=tau, precision=precision,
-           max_diff=float(np.max(np.abs(out[0] - out[1]))))
-    assert np.array_equal(out[0], out[1])
-
-
-def test_d3q19_three_pass_limits():
-    """Kernel 4 is the D3Q19 step (any N, any tau) and the automatic choice
-    there; a D2Q9 simulation rejects it with EINVAL."""
-    capi = _capi()
-    cases = [(0, (40, 30), 3, 1.0, False), (1, (20, 6, 5), 3, 1.3, True),
-             (1, (20, 6, 5), 12, 1.0, True), (1, (20, 6, 5), 10, 1.0, True)]
-    for lattice, shape, N, tau, ok in cases:
-        wl = W.random_droplet(N, shape, seed=3, lattice=lattice)
-        wl.tau = tau
-        sim = capi.Simulation(wl.gpu_mixture(), lattice, 0, shape, wl.rho)
-        auto = sim.get_tuning()["kernel"]
-        if ok:
-            assert auto == 4
-            sim.set_tuning(1, 0)
-            sim.set_tuning(4, 0)
-        else:
-            assert auto != 4
-            with pytest.raises(capi.FuglbmError):
-                sim.set_tuning(4, 0)
-        sim.close()
 
 
 @pytest.mark.parametrize("shape,N", [((70, 6, 5), 7), ((130, 3, 9), 3), ((129, 4, 3), 16)])
@@ -331,18 +279,16 @@ def _d3q19_big_reference():
     return _D3_BIG["wl"], _D3_BIG["rho"]
 
 
-@pytest.mark.parametrize("precision,kernel", [(0, 4), (1, 4), (0, 1)])
-def test_d3q19_largest_serving_size(precision, kernel):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_d3q19_largest_serving_size(precision):
     """The largest D3Q19 request of the serving workload: 128^3 with ten
     components (6.4 GB of FP64 populations on the GPU), 2 steps against the
-    oracle over the whole field (FP64 <= 1e-12, FP32 storage <= 1e-6), on
-    the three-pass step the library picks and on the four-pass step."""
+    oracle over the whole field (FP64 <= 1e-12, FP32 storage <= 1e-6)."""
     _capi()
     wl, ref = _d3q19_big_reference()
-    g = run_gpu(wl, 2, precision=precision, kernel=kernel)
-    assert g["sim"].get_tuning()["kernel"] == kernel
+    g = run_gpu(wl, 2, precision=precision)
     e = rel_err(g["rho"], ref)
-    report("d3q19_128", precision=precision, kernel=kernel, rho_rel=e)
+    report("d3q19_128", precision=precision, rho_rel=e)
     g["sim"].close()
     assert g["status"] == 0
     assert e <= (1e-12 if precision == 0 else 1e-6)

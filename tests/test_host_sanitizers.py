@@ -20,8 +20,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2306_10652_amd", "csrc")
-SOURCES = ["kernels_generic.hip", "kernels_force_collide.hip", "kernels_fused2d.hip",
-           "kernels_fused2d_ws.hip",
+SOURCES = ["kernels_generic.hip", "kernels_fused2d.hip", "kernels_fused2d_ws.hip",
            "fuglbm_host.cpp"]
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang++"
