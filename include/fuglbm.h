@@ -174,10 +174,14 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
  * saw a device status bit. */
 fuglbm_status fuglbm_step_n(fuglbm_sim *sim, int64_t nsteps, void *hip_stream);
 
-/* Advance count simulations by nsteps each with one launch per step for the
- * whole set (D2Q9 simulations sharing ncomp and precision are packed into a
- * single tile table; others fall back to their own launches).  Handles must
- * be distinct.  Asynchronous on hip_stream. */
+/* Advance count simulations by nsteps each, batched: D2Q9 simulations on a
+ * fused kernel that share ncomp and precision are packed into one tile
+ * table (one launch per step); the others (D3Q19, and D2Q9 on the
+ * multi-pass kernels) that share lattice, precision and tau == 1 or not
+ * into one member table per group (each of the four multi-pass kernels
+ * launched once per step for the whole group).  Results are bitwise those
+ * of stepping each simulation alone.  Handles must be distinct.
+ * Asynchronous on hip_stream. */
 fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count, int64_t nsteps,
                                void *hip_stream);
 

@@ -1157,9 +1157,82 @@ fuglbm_status tune_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group,
 
 }  // namespace
 
+// Batched multi-pass step (D3Q19, and D2Q9 simulations on the multi-pass
+// kernels): one member table per (lattice, storage precision, tau != 1),
+// cached while the member set is the same; four launches per step over all
+// members (no tuning: the multi-pass kernels have no variants).
+struct GenBatch {
+    std::vector<fuglbm_sim *> sims;
+    std::vector<uint64_t> uids;
+    std::vector<int> parity0;
+    GenMember *dm = nullptr;
+    size_t cap = 0;
+    int64_t total[3] = {0, 0, 0};
+    hipStream_t last_stream = nullptr;
+    bool used = false;   // last_stream is meaningful
+};
+
+std::map<std::tuple<int, int, int>, GenBatch> &gen_batches() {
+    static std::map<std::tuple<int, int, int>, GenBatch> t;
+    return t;
+}
+
+fuglbm_status build_gen_batch(GenBatch &gb, const std::vector<fuglbm_sim *> &group) {
+    std::vector<GenMember> m(group.size());
+    int64_t acc[3] = {0, 0, 0};
+    for (size_t k = 0; k < group.size(); ++k) {
+        const fuglbm_sim *s = group[k];
+        int64_t u[3];
+        generic_units(s->lattice == FUGLBM_D2Q9 ? 0 : 1, s->N, s->nx, s->ny, s->nz, u);
+        GenMember &g = m[k];
+        g.c = s->dc;
+        g.buf[0] = s->buf[0];
+        g.buf[1] = s->buf[1];
+        g.rho_f = s->rho_f;
+        g.psi_f = s->psi_f;
+        g.s_f = s->s_f;
+        g.j_f = s->j_f;
+        g.u_f = s->u_f;
+        g.status = s->status;
+        for (int p = 0; p < 3; ++p) g.end[p] = (acc[p] += u[p]);
+        g.parity = s->parity;
+        g.pad = 0;
+    }
+    if (acc[0] > INT32_MAX - 8 || acc[1] > INT32_MAX - 8 || acc[2] > INT32_MAX - 8)
+        return fail(FUGLBM_EINVAL, "batch too large for one launch");
+    if (gb.cap < m.size()) {
+        if (gb.dm) HIP_TRY(hipFree(gb.dm));
+        gb.dm = nullptr;
+        gb.cap = 0;
+        HIP_TRY(hipMalloc(&gb.dm, m.size() * sizeof(GenMember)));
+        gb.cap = m.size();
+    }
+    HIP_TRY(hipMemcpy(gb.dm, m.data(), m.size() * sizeof(GenMember), hipMemcpyHostToDevice));
+    gb.sims = group;
+    gb.uids.clear();
+    gb.parity0.clear();
+    for (auto *s : group) {
+        gb.uids.push_back(s->uid);
+        gb.parity0.push_back(s->parity);
+    }
+    for (int p = 0; p < 3; ++p) gb.total[p] = acc[p];
+    return FUGLBM_OK;
+}
+
 // A destroyed simulation's buffers may be handed to someone else: drop every
 // cached table (and its captured graph) that still refers to it.
 void forget_sim_in_batches(const fuglbm_sim *s) {
+    for (auto &kv : gen_batches()) {
+        GenBatch &gb = kv.second;
+        for (size_t k = 0; k < gb.sims.size(); ++k) {
+            if (gb.sims[k] == s && gb.uids[k] == s->uid) {
+                gb.sims.clear();
+                gb.uids.clear();
+                gb.parity0.clear();
+                break;
+            }
+        }
+    }
     for (auto &kv : batch_tables()) {
         BatchTable &bt = kv.second;
         for (size_t k = 0; k < bt.sims.size(); ++k) {
@@ -1253,9 +1326,46 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             s->last_stream = st;
         }
     }
-    for (auto *s : others) {
-        fuglbm_status rc = fuglbm_step_n(s, nsteps, hip_stream);
-        if (rc != FUGLBM_OK) return rc;
+    // multi-pass members: one table per (lattice, precision, tau != 1)
+    std::map<std::tuple<int, int, int>, std::vector<fuglbm_sim *>> ggroups;
+    for (auto *s : others)
+        ggroups[{s->lattice, s->fp32 ? 1 : 0, s->hc.omega != 1.0 ? 1 : 0}].push_back(s);
+    for (auto &kv : ggroups) {
+        auto &group = kv.second;
+        GenBatch &gb = gen_batches()[kv.first];
+        // the table is shared state: launches queued on another stream must
+        // finish before this call rebuilds or reuses it
+        if (gb.used && gb.last_stream != st) HIP_TRY(hipStreamSynchronize(gb.last_stream));
+        gb.last_stream = st;
+        gb.used = true;
+        bool same = gb.sims.size() == group.size();
+        for (size_t k = 0; same && k < group.size(); ++k)
+            same = gb.sims[k] == group[k] && gb.uids[k] == group[k]->uid;
+        int flip = 0;
+        if (same) {
+            flip = group[0]->parity ^ gb.parity0[0];
+            for (size_t k = 0; k < group.size(); ++k)
+                if ((group[k]->parity ^ gb.parity0[k]) != flip) same = false;
+        }
+        if (!same) {
+            if (gb.used) HIP_TRY(hipStreamSynchronize(st));
+            fuglbm_status rc = build_gen_batch(gb, group);
+            if (rc != FUGLBM_OK) return rc;
+            flip = 0;
+        }
+        const int lat = std::get<0>(kv.first) == FUGLBM_D2Q9 ? 0 : 1;
+        const bool f32 = std::get<1>(kv.first) != 0, keep = std::get<2>(kv.first) != 0;
+        for (int64_t t = 0; t < nsteps; ++t) {
+            hipError_t e = launch_step_generic_batch(lat, f32, keep, gb.dm, (int)group.size(),
+                                                     gb.total, flip, st);
+            if (e != hipSuccess) return hip_fail(e, "batched multi-pass step launch");
+            flip ^= 1;
+        }
+        for (auto *s : group) {
+            s->parity ^= (int)(nsteps & 1);
+            s->step += nsteps;
+            s->last_stream = st;
+        }
     }
     if (skipped) return fail(FUGLBM_ENONFINITE, "some simulations have a sticky device error");
     return FUGLBM_OK;

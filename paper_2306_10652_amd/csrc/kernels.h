@@ -29,6 +29,27 @@ hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int nc
                                int nz, const void *gs, void *gd, double *rho_f, double *psi_f,
                                double *s_f, double *j_f, double *u_f, uint32_t *status,
                                bool keep_old, hipStream_t st);
+// One member of a batched multi-pass step (fuglbm_step_many for simulations
+// on the multi-pass kernels).  A launch reads buf[parity ^ flip] and writes
+// the other buffer.  end[p]: work units of pass p through this member,
+// cumulative over the table (p = 0: TPB-site blocks of the moments and
+// interface passes, 1: velocity tiles, 2: collision (tile, component) units).
+struct GenMember {
+    const SimConst *c;
+    void *buf[2];
+    double *rho_f, *psi_f, *s_f, *j_f, *u_f;
+    uint32_t *status;
+    int64_t end[3];
+    int32_t parity;
+    int32_t pad;
+};
+// Work units of one simulation for the three kinds of GenMember::end.
+void generic_units(int lattice, int ncomp, int nx, int ny, int nz, int64_t units[3]);
+// One step of every member (same lattice, storage precision and keep_old);
+// total[p] = members[nmembers - 1].end[p].
+hipError_t launch_step_generic_batch(int lattice, bool fp32, bool keep_old,
+                                     const GenMember *members, int nmembers,
+                                     const int64_t total[3], int flip, hipStream_t st);
 // Macroscopic fields of a state: rho_i, RT ln f_i -> psi_i, s, j and (u_f
 // non-null) the force-corrected velocity.
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int nx, int ny, int nz,

@@ -40,16 +40,19 @@ __global__ __launch_bounds__(TPB) void k_init(const SimConst *__restrict__ c,
     }
 }
 
+// Each pass is a device function over one work unit (a block of TPB sites,
+// or a tile), called by the kernel of one simulation and by the batched
+// kernel, which finds the unit's simulation in a member table.
 template <class L, typename ST>
-__global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict__ c,
-                                                     const void *__restrict__ g,
-                                                     double *__restrict__ rho_f,
-                                                     double *__restrict__ psi_f,
-                                                     double *__restrict__ s_f,
-                                                     double *__restrict__ j_f,
-                                                     uint32_t *__restrict__ status) {
+__device__ __forceinline__ void moments_eos_body(const SimConst *__restrict__ c,
+                                                 const void *__restrict__ g,
+                                                 double *__restrict__ rho_f,
+                                                 double *__restrict__ psi_f,
+                                                 double *__restrict__ s_f,
+                                                 double *__restrict__ j_f,
+                                                 uint32_t *__restrict__ status, int64_t blk) {
     const int64_t ns = c->nsites;
-    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t s = blk * TPB + threadIdx.x;
     if (s >= ns) return;
     const int N = c->N, nx = c->nx;
     const PopLayout<ST> P(N, L::Q, nx, (int64_t)c->ny * c->nz);
@@ -113,12 +116,23 @@ __global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict_
     if (bad) atomicOr(status, bad);
 }
 
+template <class L, typename ST>
+__global__ __launch_bounds__(TPB) void k_moments_eos(const SimConst *__restrict__ c,
+                                                     const void *__restrict__ g,
+                                                     double *__restrict__ rho_f,
+                                                     double *__restrict__ psi_f,
+                                                     double *__restrict__ s_f,
+                                                     double *__restrict__ j_f,
+                                                     uint32_t *__restrict__ status) {
+    moments_eos_body<L, ST>(c, g, rho_f, psi_f, s_f, j_f, status, blockIdx.x);
+}
+
 template <class L>
-__global__ __launch_bounds__(TPB) void k_interface(const SimConst *__restrict__ c,
-                                                   const double *__restrict__ s_f,
-                                                   double *__restrict__ psi_f) {
+__device__ __forceinline__ void interface_body(const SimConst *__restrict__ c,
+                                               const double *__restrict__ s_f,
+                                               double *__restrict__ psi_f, int64_t blk) {
     const int64_t ns = c->nsites;
-    const int64_t s = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t s = blk * TPB + threadIdx.x;
     if (s >= ns) return;
     const int nx = c->nx, ny = c->ny, nz = c->nz;
     const int x = (int)(s % nx), y = (int)((s / nx) % ny), z = (int)(s / ((int64_t)nx * ny));
@@ -135,6 +149,13 @@ __global__ __launch_bounds__(TPB) void k_interface(const SimConst *__restrict__ 
         const int64_t k = (int64_t)i * ns + s;
         psi_f[k] = fma(-c->sqk[i], lap, psi_f[k]);
     }
+}
+
+template <class L>
+__global__ __launch_bounds__(TPB) void k_interface(const SimConst *__restrict__ c,
+                                                   const double *__restrict__ s_f,
+                                                   double *__restrict__ psi_f) {
+    interface_body<L>(c, s_f, psi_f, blockIdx.x);
 }
 
 
@@ -154,14 +175,12 @@ __device__ __forceinline__ void collide_unit(int unit, int ntiles, int N, int &t
 
 // u = (j + F/2) / rho, F = sum_i F_i, F_i = -rt_i grad psi_i  -> u_f
 template <class L>
-__global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__ c,
-                                                    const double *__restrict__ rho_f,
-                                                    const double *__restrict__ psi_f,
-                                                    const double *__restrict__ j_f,
-                                                    double *__restrict__ u_f) {
+__device__ __forceinline__ void velocity_body(const SimConst *__restrict__ c,
+                                              const double *__restrict__ rho_f,
+                                              const double *__restrict__ psi_f,
+                                              const double *__restrict__ j_f,
+                                              double *__restrict__ u_f, int unit, double *lp) {
     using TG = TileGeom<L, TileV<L>>;
-    __shared__ double lp[TG::NH];
-    const int unit = xcd_unit();
     // padding units leave as a whole workgroup, before any barrier
     if (unit >= TG::count(c->nx, c->ny, c->nz)) return;
     const TG T(c, unit);
@@ -189,20 +208,28 @@ __global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__
     if (L::D == 3) u_f[2 * ns + s] = fma(0.5, Fz, j_f[2 * ns + s]) / rhot;
 }
 
+template <class L>
+__global__ __launch_bounds__(TPB) void k_velocity_t(const SimConst *__restrict__ c,
+                                                    const double *__restrict__ rho_f,
+                                                    const double *__restrict__ psi_f,
+                                                    const double *__restrict__ j_f,
+                                                    double *__restrict__ u_f) {
+    __shared__ double lp[TileGeom<L, TileV<L>>::NH];
+    velocity_body<L>(c, rho_f, psi_f, j_f, u_f, xcd_unit(), lp);
+}
+
 // collision (Eq. (1a)-(1c)) and push of one component over one tile
 // (collide_unit); u from u_f
 // KEEP: tau != 1, so the collision keeps (1 - omega) g of the old population.
 template <class L, typename ST, bool KEEP>
-__global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ c,
-                                                   const void *__restrict__ gs, void *__restrict__ gd,
-                                                   const double *__restrict__ rho_f,
-                                                   const double *__restrict__ psi_f,
-                                                   const double *__restrict__ u_f) {
+__device__ __forceinline__ void collide_body(const SimConst *__restrict__ c,
+                                             const void *__restrict__ gs, void *__restrict__ gd,
+                                             const double *__restrict__ rho_f,
+                                             const double *__restrict__ psi_f,
+                                             const double *__restrict__ u_f, int unit, double *lp,
+                                             double *lr) {
     using TG = TileGeom<L, TileC<L>>;
-    __shared__ double lp[TG::NH];
-    __shared__ double lr[TG::NH];
     const int N = c->N;
-    const int unit = xcd_unit();
     // padding units leave as a whole workgroup, before any barrier
     const int ntiles = (int)TG::count(c->nx, c->ny, c->nz);
     if (unit >= ntiles * N) return;
@@ -240,6 +267,77 @@ __global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ 
             collide_push_tau1<L, ST>(P, gdb, i, T.x, T.y, T.z, nx, ny, nz, r, ux, uy, uz, Fx, Fy,
                                      Fz, Gx, Gy, Gz, omega, fcoef);
     }
+}
+
+template <class L, typename ST, bool KEEP>
+__global__ __launch_bounds__(TPB) void k_collide_t(const SimConst *__restrict__ c,
+                                                   const void *__restrict__ gs, void *__restrict__ gd,
+                                                   const double *__restrict__ rho_f,
+                                                   const double *__restrict__ psi_f,
+                                                   const double *__restrict__ u_f) {
+    __shared__ double lp[TileGeom<L, TileC<L>>::NH];
+    __shared__ double lr[TileGeom<L, TileC<L>>::NH];
+    collide_body<L, ST, KEEP>(c, gs, gd, rho_f, psi_f, u_f, xcd_unit(), lp, lr);
+}
+
+// ---- batched passes: many simulations per launch (GenMember table) ------
+// The member that owns global work unit u of pass p (-1 past the last one)
+// and the unit's index within it; uniform per workgroup.
+__device__ __forceinline__ int find_member(const GenMember *__restrict__ m, int nm, int p,
+                                           int64_t u, int64_t &local) {
+    if (u >= m[nm - 1].end[p]) return -1;
+    int lo = 0, hi = nm - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (m[mid].end[p] > u)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    local = u - (lo ? m[lo - 1].end[p] : 0);
+    return lo;
+}
+
+template <class L, typename ST>
+__global__ __launch_bounds__(TPB) void k_moments_eos_b(const GenMember *__restrict__ m, int nm,
+                                                       int flip) {
+    int64_t local;
+    const int k = find_member(m, nm, 0, blockIdx.x, local);
+    if (k < 0) return;
+    const GenMember &g = m[k];
+    moments_eos_body<L, ST>(g.c, g.buf[g.parity ^ flip], g.rho_f, g.psi_f, g.s_f, g.j_f, g.status,
+                            local);
+}
+
+template <class L>
+__global__ __launch_bounds__(TPB) void k_interface_b(const GenMember *__restrict__ m, int nm) {
+    int64_t local;
+    const int k = find_member(m, nm, 0, blockIdx.x, local);
+    if (k < 0) return;
+    interface_body<L>(m[k].c, m[k].s_f, m[k].psi_f, local);
+}
+
+template <class L>
+__global__ __launch_bounds__(TPB) void k_velocity_b(const GenMember *__restrict__ m, int nm) {
+    __shared__ double lp[TileGeom<L, TileV<L>>::NH];
+    int64_t local;
+    const int k = find_member(m, nm, 1, xcd_unit(), local);
+    if (k < 0) return;
+    const GenMember &g = m[k];
+    velocity_body<L>(g.c, g.rho_f, g.psi_f, g.j_f, g.u_f, (int)local, lp);
+}
+
+template <class L, typename ST, bool KEEP>
+__global__ __launch_bounds__(TPB) void k_collide_b(const GenMember *__restrict__ m, int nm,
+                                                   int flip) {
+    __shared__ double lp[TileGeom<L, TileC<L>>::NH];
+    __shared__ double lr[TileGeom<L, TileC<L>>::NH];
+    int64_t local;
+    const int k = find_member(m, nm, 2, xcd_unit(), local);
+    if (k < 0) return;
+    const GenMember &g = m[k];
+    collide_body<L, ST, KEEP>(g.c, g.buf[g.parity ^ flip], g.buf[g.parity ^ flip ^ 1], g.rho_f,
+                              g.psi_f, g.u_f, (int)local, lp, lr);
 }
 
 // Diagnostics from the macroscopic fields of the current state (rho_i,
@@ -408,6 +506,44 @@ hipError_t launch_step_generic(int lattice, bool fp32, const SimConst *c, int nc
                     : step_generic_t<D2Q9, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
     return fp32 ? step_generic_t<D3Q19, float>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st)
                 : step_generic_t<D3Q19, double>(c, ncomp, ns, nx, ny, nz, gs, gd, rho_f, psi_f, s_f, j_f, u_f, status, k, st);
+}
+
+void generic_units(int lattice, int ncomp, int nx, int ny, int nz, int64_t units[3]) {
+    units[0] = ((int64_t)nx * ny * nz + TPB - 1) / TPB;
+    if (lattice == 0) {
+        units[1] = TileGeom<D2Q9, TileV<D2Q9>>::count(nx, ny, nz);
+        units[2] = TileGeom<D2Q9, TileC<D2Q9>>::count(nx, ny, nz) * ncomp;
+    } else {
+        units[1] = TileGeom<D3Q19, TileV<D3Q19>>::count(nx, ny, nz);
+        units[2] = TileGeom<D3Q19, TileC<D3Q19>>::count(nx, ny, nz) * ncomp;
+    }
+}
+
+template <class L, typename ST>
+hipError_t step_batch_t(bool keep, const GenMember *m, int nm, const int64_t total[3], int flip,
+                        hipStream_t st) {
+    const unsigned nb = (unsigned)total[0];
+    const unsigned vb = unit_blocks(total[1]);
+    const unsigned cb = unit_blocks(total[2]);
+    hipLaunchKernelGGL((k_moments_eos_b<L, ST>), dim3(nb), dim3(TPB), 0, st, m, nm, flip);
+    hipLaunchKernelGGL((k_interface_b<L>), dim3(nb), dim3(TPB), 0, st, m, nm);
+    hipLaunchKernelGGL((k_velocity_b<L>), dim3(vb), dim3(TPB), 0, st, m, nm);
+    if (keep)
+        hipLaunchKernelGGL((k_collide_b<L, ST, true>), dim3(cb), dim3(TPB), 0, st, m, nm, flip);
+    else
+        hipLaunchKernelGGL((k_collide_b<L, ST, false>), dim3(cb), dim3(TPB), 0, st, m, nm, flip);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_generic_batch(int lattice, bool fp32, bool keep_old,
+                                     const GenMember *members, int nmembers,
+                                     const int64_t total[3], int flip, hipStream_t st) {
+    if (nmembers < 1) return hipSuccess;
+    if (lattice == 0)
+        return fp32 ? step_batch_t<D2Q9, float>(keep_old, members, nmembers, total, flip, st)
+                    : step_batch_t<D2Q9, double>(keep_old, members, nmembers, total, flip, st);
+    return fp32 ? step_batch_t<D3Q19, float>(keep_old, members, nmembers, total, flip, st)
+                : step_batch_t<D3Q19, double>(keep_old, members, nmembers, total, flip, st);
 }
 
 hipError_t launch_fields(int lattice, bool fp32, const SimConst *c, int nx, int ny, int nz,

@@ -3,9 +3,10 @@
 Requests (a mixture, a lattice and grid, an initial field) arrive over time.
 A request is admitted as soon as its device memory fits the HBM budget and
 a slot is free; from then on it shares the GPU with every other admitted
-request: each tick advances all active D2Q9 simulations with one batched
-launch per step per component count (``fuglbm_step_many``) and the D3Q19
-ones with their own launches.  These units of work go longest-first onto
+request: each tick advances all active simulations with batched launches
+(``fuglbm_step_many``): one per step per (component count, precision) for
+D2Q9, four per step (the multi-pass kernels) per precision for D3Q19.
+These units of work go longest-first onto
 the least-loaded of a few HIP streams (default priority), so launches of
 different groups run side by side on the CUs; then every simulation's residual is read
 (``fuglbm_diagnostics``, on the stream that stepped it).  A simulation
@@ -130,16 +131,15 @@ class Server:
                     time.sleep(max(0.0, min(0.05, pending[0][0] - (clock() - t0))))
                 continue
             # one tick: every active simulation advances `chunk` steps; units
-            # of work (a batched D2Q9 group, a D3Q19 simulation) round-robin
-            # over the streams
+            # of work (a batched D2Q9 group of one component count and
+            # precision, a batched D3Q19 group of one precision) go onto the
+            # streams
             groups = {}
-            units = []
             for s in active:
-                if s["req"].lattice == capi.D2Q9:
-                    groups.setdefault((s["req"].N, s["req"].precision), []).append(s)
-                else:
-                    units.append([s])
-            units = list(groups.values()) + units
+                r = s["req"]
+                key = (r.lattice, r.N if r.lattice == capi.D2Q9 else 0, r.precision)
+                groups.setdefault(key, []).append(s)
+            units = list(groups.values())
             # longest-first onto the least-loaded stream (work ~ CSU per step)
             cost = lambda u: sum(int(np.prod(s["req"].shape)) * s["req"].N *
                                  (19 if s["req"].lattice != capi.D2Q9 else 9) for s in u)
@@ -148,15 +148,11 @@ class Server:
                 k = min(range(len(load)), key=load.__getitem__)
                 load[k] += cost(unit)
                 st = self.streams[k]
-                if unit[0]["req"].lattice == capi.D2Q9:
-                    rc = capi.fuglbm_step_many([s["sim"] for s in unit], self.chunk, st)
-                    if rc not in (0, 5):
-                        capi.check(rc)
-                else:
-                    try:
-                        unit[0]["sim"].step_n(self.chunk, st)
-                    except capi.FuglbmError:
-                        pass    # sticky: the residual read below retires it alone
+                # ENONFINITE: a member with a sticky error was skipped; the
+                # residual read below retires it alone
+                rc = capi.fuglbm_step_many([s["sim"] for s in unit], self.chunk, st)
+                if rc not in (0, 5):
+                    capi.check(rc)
             still = []
             for s in active:
                 req = s["req"]

@@ -23,9 +23,10 @@ def make(wl, precision=0, capi=None):
 @pytest.mark.parametrize("lattice", [0, 1])
 def test_mass_conservation(lattice, precision):
     """Every component's mass after 2000 steps, both lattices and both
-    precisions: with FP32 storage each step folds the rounding error of a
-    site's moving populations into its FP64 rest population, so the mass is
-    conserved to FP64 rounding as in FP64 storage (bound 1e-12)."""
+    precisions: with FP32 storage each step stores a site's FP64 rest
+    population as rho_i minus the FP64 sum of its stored moving populations,
+    so the mass is conserved to FP64 rounding as in FP64 storage (bound
+    1e-12)."""
     wl = W.droplet64() if lattice == 0 else W.random_droplet(3, (20, 18, 16), seed=5, lattice=1)
     sim = make(wl, precision)
     d0 = sim.diagnostics()
@@ -70,9 +71,10 @@ def test_bitwise_determinism_and_batched_equals_single():
 def test_heterogeneous_batch_and_degenerate_calls():
     """One step_many call over simulations that differ in component count,
     precision and lattice (grouped into one launch per (N, precision) for
-    D2Q9, stepped alone for D3Q19): each ends bitwise where stepping it
-    alone ends.  Degenerate calls: zero steps and an empty batch change
-    nothing; a repeated simulation or negative steps are EINVAL."""
+    D2Q9, one set of multi-pass launches per precision for D3Q19): each ends
+    bitwise where stepping it alone ends.  Degenerate calls: zero steps and
+    an empty batch change nothing; a repeated simulation or negative steps
+    are EINVAL."""
     capi = _capi()
     cases = [(W.random_droplet(3, (67, 45), seed=1), 0), (W.random_droplet(3, (40, 33), seed=2), 0),
              (W.random_droplet(3, (50, 50), seed=3), 1), (W.random_droplet(5, (61, 29), seed=4), 0),
@@ -97,6 +99,54 @@ def test_heterogeneous_batch_and_degenerate_calls():
         assert s.diagnostics()["step"] == 41
     assert capi.fuglbm_step_many([sims[0], sims[1], sims[0]], 5) == 1
     assert capi.fuglbm_step_many(sims[:2], -1) == 1
+
+
+def test_batched_multipass_members_bitwise():
+    """The multi-pass members of step_many (D3Q19 of different component
+    counts and grid shapes, both precisions, one at tau = 1.3, and a D2Q9
+    simulation on the multi-pass kernels) share one member table per
+    (lattice, precision, tau class) and one launch per pass: each ends
+    bitwise where stepping it alone ends, over two calls (17 then 24 steps:
+    the second call reuses the table with the parity flipped) and again
+    after one member is destroyed (the table is rebuilt)."""
+    capi = _capi()
+    cases = [(2, (9, 8, 7), 21, 1, 1.0, 0), (3, (20, 6, 5), 22, 1, 1.0, 1),
+             (5, (33, 5, 9), 23, 1, 1.0, 0), (10, (64, 2, 10), 24, 1, 1.0, 0),
+             (3, (20, 6, 5), 25, 1, 1.3, 0), (4, (70, 12), 26, 0, 1.0, 0),
+             (5, (33, 5, 9), 23, 1, 1.0, 1)]
+    wls = []
+    for N, shape, seed, lat, tau, prec in cases:
+        wl = W.random_droplet(N, shape, seed=seed, lattice=lat)
+        wl.tau = tau
+        wls.append((wl, prec))
+
+    def fresh(wl, prec):
+        s = make(wl, prec, capi=capi)
+        if wl.lattice == 0:
+            s.set_tuning(1, 0)     # D2Q9 on the multi-pass kernels
+        return s
+
+    alone41, alone46 = [], []
+    for wl, prec in wls:
+        s = fresh(wl, prec)
+        s.step_n(41)
+        alone41.append(s.read_populations())
+        s.step_n(5)
+        alone46.append(s.read_populations())
+        s.close()
+    sims = [fresh(wl, prec) for wl, prec in wls]
+    capi.step_many(sims, 17)
+    capi.step_many(sims, 24)
+    for s, ref in zip(sims, alone41):
+        assert np.array_equal(s.read_populations(), ref)
+        assert s.diagnostics()["step"] == 41
+    sims[2].close()
+    rest = sims[:2] + sims[3:]
+    capi.step_many(rest, 5)
+    for s, ref in zip(rest, alone46[:2] + alone46[3:]):
+        assert np.array_equal(s.read_populations(), ref)
+    for s in rest:
+        s.close()
 
 
 def test_fused_and_generic_kernels_agree():
