@@ -367,31 +367,41 @@ struct Timer {
 // Times `launch` (TUNE_LAUNCHES back-to-back launches) after `prepare(r)`
 // for every candidate r; returns the fastest.
 template <class Prep, class Launch>
+// Candidates are timed in two passes, in order and then in reverse order,
+// and ranked by the sum: the GPU's clocks still rise during the first
+// hundreds of milliseconds of sustained work, so a single pass would favour
+// the candidates timed last.
 fuglbm_status time_candidates(const std::vector<int> &cand, hipStream_t st, Prep prepare,
                               Launch launch, int &best, float *best_time = nullptr) {
     Timer tm;
     if (!tm.ok()) return fail(FUGLBM_EDEVICE, "hipEventCreate");
-    float best_ms = 1e30f;
-    best = cand.empty() ? 0 : cand[0];
+    std::vector<float> sum(cand.size(), 0.f);
     bool warm = false;
-    for (size_t k = 0; k < cand.size(); ++k) {
-        fuglbm_status rc = prepare(cand[k]);
-        if (rc != FUGLBM_OK) return rc;
-        if (!warm) {   // first launch of the kernel: not timed
-            HIP_TRY(launch());
-            warm = true;
-        }
-        HIP_TRY(hipEventRecord(tm.a, st));
-        for (int j = 0; j < TUNE_LAUNCHES; ++j) HIP_TRY(launch());
-        HIP_TRY(hipEventRecord(tm.b, st));
-        HIP_TRY(hipEventSynchronize(tm.b));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, tm.a, tm.b));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = cand[k];
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t q = 0; q < cand.size(); ++q) {
+            const size_t k = pass == 0 ? q : cand.size() - 1 - q;
+            fuglbm_status rc = prepare(cand[k]);
+            if (rc != FUGLBM_OK) return rc;
+            if (!warm) {   // first launch of the kernel: not timed
+                HIP_TRY(launch());
+                warm = true;
+            }
+            HIP_TRY(hipEventRecord(tm.a, st));
+            for (int j = 0; j < TUNE_LAUNCHES; ++j) HIP_TRY(launch());
+            HIP_TRY(hipEventRecord(tm.b, st));
+            HIP_TRY(hipEventSynchronize(tm.b));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, tm.a, tm.b));
+            sum[k] += ms;
         }
     }
+    float best_ms = 1e30f;
+    best = cand.empty() ? 0 : cand[0];
+    for (size_t k = 0; k < cand.size(); ++k)
+        if (sum[k] < best_ms) {
+            best_ms = sum[k];
+            best = cand[k];
+        }
     if (best_time) *best_time = best_ms;
     return FUGLBM_OK;
 }
@@ -457,7 +467,9 @@ fuglbm_status autotune_rows(fuglbm_sim *s, hipStream_t st) {
         FusedItem *dev = tables.p;
         HIP_TRY(hipStreamSynchronize(st));
         HIP_TRY(hipMemcpy(dev, all.data(), all.size() * sizeof(FusedItem), hipMemcpyHostToDevice));
-        std::vector<Timer> tm(cand.size());
+        // two passes, in order and in reverse order, ranked by the sum (see
+        // time_candidates), queued back to back with one wait at the end
+        std::vector<Timer> tm(2 * cand.size());
         for (auto &t : tm)
             if (!t.ok()) return fail(FUGLBM_EDEVICE, "hipEventCreate");
         // the trial launches read the current state and write the spare
@@ -466,17 +478,22 @@ fuglbm_status autotune_rows(fuglbm_sim *s, hipStream_t st) {
             return launch_fused(c.kernel, s->N, s->fp32, dev + c.off, (int)c.n, s->fsim, s->parity,
                                 st);
         };
-        HIP_TRY(launch(cand[0]));   // first launch of the kernel: not timed
-        for (size_t i = 0; i < cand.size(); ++i) {
-            HIP_TRY(hipEventRecord(tm[i].a, st));
+        for (size_t i = 0; i < cand.size(); ++i)   // first launch of each variant: not timed
+            if (i == 0 || cand[i].kernel != cand[i - 1].kernel) HIP_TRY(launch(cand[i]));
+        const size_t nc = cand.size();
+        for (size_t q = 0; q < 2 * nc; ++q) {
+            const size_t i = q < nc ? q : 2 * nc - 1 - q;
+            HIP_TRY(hipEventRecord(tm[q].a, st));
             for (int j = 0; j < TUNE_LAUNCHES; ++j) HIP_TRY(launch(cand[i]));
-            HIP_TRY(hipEventRecord(tm[i].b, st));
+            HIP_TRY(hipEventRecord(tm[q].b, st));
         }
         HIP_TRY(hipEventSynchronize(tm.back().b));
         float best_ms = 1e30f;
-        for (size_t i = 0; i < cand.size(); ++i) {
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, tm[i].a, tm[i].b));
+        for (size_t i = 0; i < nc; ++i) {
+            float m1 = 0.f, m2 = 0.f;
+            HIP_TRY(hipEventElapsedTime(&m1, tm[i].a, tm[i].b));
+            HIP_TRY(hipEventElapsedTime(&m2, tm[2 * nc - 1 - i].a, tm[2 * nc - 1 - i].b));
+            const float ms = m1 + m2;
             if (ms < best_ms) {
                 best_ms = ms;
                 best_k = cand[i].kernel;
