@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "spinodal10_d2q9_1024x1024"
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fused_d2q9_spinodal10_1024_pmc.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2306_10652_amd", "csrc", f)
-               for f in ("fused_common.h", "kernels_fused2d.hip", "kernels_fused2d_ws.hip")]
+               for f in ("lbm_common.h", "fused_common.h", "kernels_fused2d.hip",
+                         "kernels_fused2d_ws.hip")]
 KERNEL_NAMES = {2: "k_fused_d2q9<10,%s>", 3: "k_fused_d2q9_ws<10,%s>"}
 
 

@@ -109,8 +109,13 @@ def test_fields_bytes():
     pop32 = 2 * (8 + 8 * 4) * 10 * 1024 * 1024
     # FP64 rows are padded to a pitch of 1024 + 16 (workspace is the same)
     pad64 = 2 * 9 * 10 * 8 * 16 * 1024
-    # FP32 arrays are 64 elements apart beyond the grid
-    pad32 = 2 * (8 + 8 * 4) * 10 * 64
+    # FP32 arrays are 2^16 + 64 elements apart beyond the grid from 2^20
+    # sites on, 64 elements below
+    pad32 = 2 * (8 + 8 * 4) * 10 * (65536 + 64)
     assert b64 >= pop64 and b64 - b32 == pop64 + pad64 - pop32 - pad32
+    n = 512
+    s64 = L.fuglbm_fields_bytes(10, capi.D2Q9, capi.FP64, n, n, 1)
+    s32 = L.fuglbm_fields_bytes(10, capi.D2Q9, capi.FP32_STORAGE, n, n, 1)
+    assert s64 - s32 == (2 * 9 * 10 * 8 * n * (n + 16)) - 2 * (8 + 8 * 4) * 10 * (n * n + 64)
     assert L.fuglbm_fields_bytes(0, 0, 0, 8, 8, 1) == 0
     assert L.fuglbm_fields_bytes(3, 1, 0, 8, 8, 8) >= 2 * 19 * 3 * 8 * 512
