@@ -463,6 +463,23 @@ def trace_summary(db_path, steps, steady=0):
             "%.1f" % (sum(tail) / len(tail)) if tail else "-"))
 
 
+def marker_summary(db_path):
+    """The library's roctx ranges (one per C-ABI call that launches work)
+    from a rocprofv3 --marker-trace results database: calls, total and mean
+    host time per range name.  Prints a markdown table."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    agg = {}
+    for start, end, ext in db.execute("select start, end, extdata from regions "
+                                      "where category = 'MARKER_CORE_RANGE_API' order by start"):
+        name = json.loads(ext or "{}").get("message", "?")
+        agg.setdefault(name, []).append((end - start) / 1e6)
+    print("| range | calls | total ms | mean ms | max ms |")
+    print("|---|---|---|---|---|")
+    for name, d in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        print("| `%s` | %d | %.2f | %.3f | %.3f |" % (name, len(d), sum(d), sum(d) / len(d), max(d)))
+
+
 def _counter_values(db_path, counter):
     """(kernel name, value) of every dispatch in a rocprofv3 counter-collection
     database, in dispatch order."""
@@ -539,6 +556,9 @@ def main():
                     help="only summarise a rocprofv3 results database of a kernel-trace run "
                          "of this script (per-kernel durations; the last --steps dispatches "
                          "of each kernel are the timed window)")
+    ap.add_argument("--marker-summary", default=None,
+                    help="print the library's roctx ranges from a rocprofv3 --marker-trace "
+                         "results database and exit")
     ap.add_argument("--pmc-summary", nargs=7, default=None,
                     metavar=("OUT", "FETCH64", "WRITE64", "FETCH32", "WRITE32", "CALIB_FETCH",
                              "CALIB_WRITE"),
@@ -551,6 +571,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args.trace_summary, args.steps, args.steady_steps)
+        return
+    if args.marker_summary:
+        marker_summary(args.marker_summary)
         return
     if args.calib_copy_mib:
         import torch

@@ -13,8 +13,19 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/fuglbm.h"
 #include "kernels.h"
+
+// A roctx range over one library call (visible with rocprofv3
+// --marker-trace beside the kernels the call launches).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 namespace {
 
@@ -427,6 +438,7 @@ fuglbm_status set_rows(fuglbm_sim *s, int rows, hipStream_t st) {
 // the same sustained load (with a host wait between candidates the clocks
 // fall back and the early candidates run slower).
 fuglbm_status autotune_rows(fuglbm_sim *s, hipStream_t st) {
+    const TraceRange trace_range("fuglbm autotune rows");
     const bool both = s->auto_kernel && ws_usable(s->N, s->fp32);
     const int tag = both ? 0 : s->kernel;
     const auto key = std::make_tuple(s->nx, s->ny, s->N, (s->fp32 ? 1 : 0) + 2 * tag);
@@ -616,6 +628,7 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
                                  fuglbm_precision prec, int32_t nx, int32_t ny, int32_t nz,
                                  const double *rho, void *dev_buf, void *hip_stream,
                                  fuglbm_sim **out) {
+    const TraceRange trace_range("fuglbm_init_fields");
     if (!mix || !rho || !out) return fail(FUGLBM_EINVAL, "null argument");
     *out = nullptr;
     if (lattice != FUGLBM_D2Q9 && lattice != FUGLBM_D3Q19) return fail(FUGLBM_EINVAL, "lattice");
@@ -798,6 +811,7 @@ fuglbm_status fuglbm_sim_info(const fuglbm_sim *s, int32_t *Q, int32_t *D, int64
 }
 
 fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
+    const TraceRange trace_range("fuglbm_step_n");
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
     if (nsteps < 0) return fail(FUGLBM_EINVAL, "nsteps must be >= 0");
     if (s->sticky) return fail(FUGLBM_ENONFINITE, "simulation has a sticky device error");
@@ -836,6 +850,7 @@ fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
 
 fuglbm_status fuglbm_read_moments(fuglbm_sim *s, double *rho_out, double *u_out,
                                   fuglbm_diag *diag) {
+    const TraceRange trace_range("fuglbm_read_moments");
     if (!s) return fail(FUGLBM_EINVAL, "null sim");
     hipStream_t st = s->last_stream;
     HIP_TRY(hipStreamSynchronize(st));
@@ -861,6 +876,7 @@ fuglbm_status fuglbm_read_moments(fuglbm_sim *s, double *rho_out, double *u_out,
 // state), then per-block partial sums and one fixed-order final sum per
 // quantity on the device; the host reads the (N + 1) x DIAG_QUANT totals.
 fuglbm_status fuglbm_diagnostics(fuglbm_sim *s, fuglbm_diag *diag) {
+    const TraceRange trace_range("fuglbm_diagnostics");
     if (!s || !diag) return fail(FUGLBM_EINVAL, "null argument");
     hipStream_t st = s->last_stream;
     const int nblk = diag_blocks(s->ns);
@@ -1269,6 +1285,7 @@ void forget_sim_in_batches(const fuglbm_sim *s) {
 
 extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count, int64_t nsteps,
                                           void *hip_stream) {
+    const TraceRange trace_range("fuglbm_step_many");
     if (count < 0 || (count > 0 && !sims)) return fail(FUGLBM_EINVAL, "bad sims array");
     if (nsteps < 0) return fail(FUGLBM_EINVAL, "nsteps must be >= 0");
     hipStream_t st = (hipStream_t)hip_stream;
@@ -1488,6 +1505,7 @@ fuglbm_status na_scratch(char **out) {
 
 extern "C" fuglbm_status fuglbm_step_many_noalloc(fuglbm_sim *const *sims, int32_t count,
                                                   int64_t nsteps, void *hip_stream) {
+    const TraceRange trace_range("fuglbm_step_many_noalloc");
     if (count < 0 || (count > 0 && !sims)) return fail(FUGLBM_EINVAL, "bad sims array");
     if (nsteps < 0) return fail(FUGLBM_EINVAL, "nsteps must be >= 0");
     if (count > NA_MAX_MEMBERS)

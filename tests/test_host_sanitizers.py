@@ -56,7 +56,8 @@ def driver(tmp_path_factory):
             pytest.fail("sanitizer build failed:\n" + err[-3000:])
     exe = str(out / "host_san")
     r = subprocess.run([CLANG, "-fsanitize=address,undefined"] + objs +
-                       ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lamdhip64", "-o", exe],
+                       ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lamdhip64",
+                        "-lrocprofiler-sdk-roctx", "-o", exe],
                        capture_output=True, text=True)
     if r.returncode != 0:
         pytest.fail("sanitizer link failed:\n" + r.stderr[-3000:])
