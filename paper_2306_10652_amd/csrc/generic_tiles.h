@@ -175,6 +175,21 @@ struct TileGeom {
     }
 };
 
+// Store of one new population.  Where the layout keeps a collision's
+// stores in whole aligned rows (L::PULL_X, see pop_col), nontemporal: the
+// values are read again only by the next step's moments pass, after the
+// whole field has been written (D3Q19 at 128^3 x 10: the step 2.9 % faster
+// in FP64, 2.1 % with FP32 storage).  Shifted rows (D2Q9) share their edge
+// lines with the neighbouring tiles and rely on L2 to merge those partial
+// writes: plain stores.
+template <class L, typename T>
+__device__ __forceinline__ void put_pop(T *p, T v) {
+    if constexpr (L::PULL_X)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // Collision of component i at one site at tau = 1, Eq. (1a)-(1c) with
 // omega = 1: the old population drops out, so it is not read (its moments
 // came from the moments pass), and the terms of the site are taken out of
@@ -234,7 +249,7 @@ __device__ __forceinline__ void collide_push_tau1(const PopLayout<ST> &P, char *
         xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
         yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
         zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-        *(ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)) = v;
+        put_pop<L>((ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)), v);
     }
     double o0;
     if constexpr (sizeof(ST) == 4)
@@ -242,7 +257,7 @@ __device__ __forceinline__ void collide_push_tau1(const PopLayout<ST> &P, char *
     else
         o0 = collide_one<L>(0, 0.0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu, omega,
                             fcoef);
-    *(double *)(gdb + P.rest((int64_t)y + (int64_t)ny * z, i, x)) = o0;
+    put_pop<L>((double *)(gdb + P.rest((int64_t)y + (int64_t)ny * z, i, x)), o0);
 }
 
 // Collision of component i at one site at tau != 1 (Eq. (1a)-(1c)): reads
@@ -273,7 +288,7 @@ __device__ __forceinline__ void collide_push_keep(const PopLayout<ST> &P, const 
         xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
         yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
         zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
-        *(ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)) = v;
+        put_pop<L>((ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)), v);
     };
     // rolled: unrolled, the compiler hoists every load and the kernel needs
     // 256 registers (one wavefront per SIMD)
@@ -282,7 +297,7 @@ __device__ __forceinline__ void collide_push_keep(const PopLayout<ST> &P, const 
     const double g0 = *(const double *)(gsb + P.rest(row, i, x));
     const double o0 = collide_one<L>(0, g0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu,
                                      omega, fcoef);
-    *(double *)(gdb + P.rest(row, i, x)) = sizeof(ST) == 4 ? o0 - err : o0;
+    put_pop<L>((double *)(gdb + P.rest(row, i, x)), sizeof(ST) == 4 ? o0 - err : o0);
 }
 
 }  // namespace
