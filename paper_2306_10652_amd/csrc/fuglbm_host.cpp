@@ -1382,7 +1382,9 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
                 if ((group[k]->parity ^ gb.parity0[k]) != flip) same = false;
         }
         if (!same) {
-            if (gb.used) HIP_TRY(hipStreamSynchronize(st));
+            // launches queued on st may still read the table that the
+            // rebuild overwrites (the upload is not ordered after them)
+            HIP_TRY(hipStreamSynchronize(st));
             fuglbm_status rc = build_gen_batch(gb, group);
             if (rc != FUGLBM_OK) return rc;
             flip = 0;
