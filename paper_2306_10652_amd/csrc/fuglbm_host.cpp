@@ -1193,7 +1193,8 @@ fuglbm_status tune_batch(BatchTable &bt, const std::vector<fuglbm_sim *> &group,
 // Batched multi-pass step (D3Q19, and D2Q9 simulations on the multi-pass
 // kernels): one member table per (lattice, storage precision, tau != 1),
 // cached while the member set is the same; four launches per step over all
-// members (no tuning: the multi-pass kernels have no variants).
+// members (no tuning: the multi-pass kernels have no variants), runs of
+// GRAPH_STEPS steps replayed from a captured graph as for the fused tables.
 struct GenBatch {
     std::vector<fuglbm_sim *> sims;
     std::vector<uint64_t> uids;
@@ -1201,9 +1202,45 @@ struct GenBatch {
     GenMember *dm = nullptr;
     size_t cap = 0;
     int64_t total[3] = {0, 0, 0};
+    int lattice = 0, fp32 = 0, keep = 0;
+    hipGraphExec_t graph = nullptr;   // GRAPH_STEPS steps starting at flip 0
     hipStream_t last_stream = nullptr;
     bool used = false;   // last_stream is meaningful
 };
+
+hipError_t gen_batch_step(const GenBatch &gb, int flip, hipStream_t st) {
+    return launch_step_generic_batch(gb.lattice, gb.fp32 != 0, gb.keep != 0, gb.dm,
+                                     (int)gb.sims.size(), gb.total, flip, st);
+}
+
+void drop_gen_graph(GenBatch &gb) {
+    if (gb.graph) (void)hipGraphExecDestroy(gb.graph);
+    gb.graph = nullptr;
+}
+
+fuglbm_status gen_batch_graph(GenBatch &gb) {
+    if (gb.graph) return FUGLBM_OK;
+    hipStream_t cs = capture_stream();
+    if (!cs) return fail(FUGLBM_EDEVICE, "cannot create capture stream");
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < GRAPH_STEPS; ++k) {
+        hipError_t e = gen_batch_step(gb, k & 1, cs);
+        if (e != hipSuccess) {
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(cs, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+            return hip_fail(e, "multi-pass batch capture");
+        }
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(cs, &g));
+    hipError_t e = hipGraphInstantiate(&gb.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        gb.graph = nullptr;
+        return hip_fail(e, "hipGraphInstantiate (multi-pass batch)");
+    }
+    return FUGLBM_OK;
+}
 
 std::map<std::tuple<int, int, int>, GenBatch> &gen_batches() {
     static std::map<std::tuple<int, int, int>, GenBatch> t;
@@ -1249,6 +1286,10 @@ fuglbm_status build_gen_batch(GenBatch &gb, const std::vector<fuglbm_sim *> &gro
         gb.parity0.push_back(s->parity);
     }
     for (int p = 0; p < 3; ++p) gb.total[p] = acc[p];
+    gb.lattice = group[0]->lattice == FUGLBM_D2Q9 ? 0 : 1;
+    gb.fp32 = group[0]->fp32 ? 1 : 0;
+    gb.keep = group[0]->hc.omega != 1.0 ? 1 : 0;
+    drop_gen_graph(gb);   // captured with the old table's size
     return FUGLBM_OK;
 }
 
@@ -1259,6 +1300,7 @@ void forget_sim_in_batches(const fuglbm_sim *s) {
         GenBatch &gb = kv.second;
         for (size_t k = 0; k < gb.sims.size(); ++k) {
             if (gb.sims[k] == s && gb.uids[k] == s->uid) {
+                drop_gen_graph(gb);
                 gb.sims.clear();
                 gb.uids.clear();
                 gb.parity0.clear();
@@ -1389,11 +1431,24 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             if (rc != FUGLBM_OK) return rc;
             flip = 0;
         }
-        const int lat = std::get<0>(kv.first) == FUGLBM_D2Q9 ? 0 : 1;
-        const bool f32 = std::get<1>(kv.first) != 0, keep = std::get<2>(kv.first) != 0;
-        for (int64_t t = 0; t < nsteps; ++t) {
-            hipError_t e = launch_step_generic_batch(lat, f32, keep, gb.dm, (int)group.size(),
-                                                     gb.total, flip, st);
+        int64_t left = nsteps;
+        if (left >= 2 * GRAPH_STEPS && flip == 1) {
+            hipError_t e = gen_batch_step(gb, flip, st);
+            if (e != hipSuccess) return hip_fail(e, "batched multi-pass step launch");
+            flip = 0;
+            --left;
+        }
+        if (left >= GRAPH_STEPS && flip == 0) {
+            // replay a captured run of GRAPH_STEPS steps (even: parity returns)
+            fuglbm_status rc = gen_batch_graph(gb);
+            if (rc != FUGLBM_OK) return rc;
+            while (left >= GRAPH_STEPS) {
+                HIP_TRY(hipGraphLaunch(gb.graph, st));
+                left -= GRAPH_STEPS;
+            }
+        }
+        for (; left > 0; --left) {
+            hipError_t e = gen_batch_step(gb, flip, st);
             if (e != hipSuccess) return hip_fail(e, "batched multi-pass step launch");
             flip ^= 1;
         }

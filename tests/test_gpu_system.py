@@ -107,18 +107,26 @@ def test_batched_multipass_members_bitwise():
     simulation on the multi-pass kernels) share one member table per
     (lattice, precision, tau class) and one launch per pass: each ends
     bitwise where stepping it alone ends, over two calls (17 then 24 steps:
-    the second call reuses the table with the parity flipped) and again
+    the second call reuses the table with the parity flipped), over three
+    calls of 70 steps (one step to even parity, two replays of the captured
+    32-step graph, the rest launched; checked after every call), and again
     after one member is destroyed (the table is rebuilt)."""
     capi = _capi()
     cases = [(2, (9, 8, 7), 21, 1, 1.0, 0), (3, (20, 6, 5), 22, 1, 1.0, 1),
-             (5, (33, 5, 9), 23, 1, 1.0, 0), (10, (64, 2, 10), 24, 1, 1.0, 0),
-             (3, (20, 6, 5), 25, 1, 1.3, 0), (4, (70, 12), 26, 0, 1.0, 0),
-             (5, (33, 5, 9), 23, 1, 1.0, 1)]
+             (5, (33, 5, 9), 23, 1, 1.0, 0), (3, (20, 6, 5), 25, 1, 1.3, 0),
+             (4, (70, 12), 26, 0, 1.0, 0), (5, (33, 5, 9), 23, 1, 1.0, 1)]
     wls = []
     for N, shape, seed, lat, tau, prec in cases:
         wl = W.random_droplet(N, shape, seed=seed, lattice=lat)
         wl.tau = tau
         wls.append((wl, prec))
+    # ten components: the spinodal mixture of the headline field on a thin
+    # 3-D grid (a random ten-component drop leaves the EOS domain)
+    from inputs import components as C, fields as Fi
+    st = W.states()["spinodal10"]
+    rho = Fi.add_noise(Fi.uniform(64, 2, st["rho_uniform"], nz=10), 1e-2, 24)
+    wls.insert(3, (W.Workload(C.N_ALKANES, 325.0, rho, (64, 2, 10), kij=np.array(st["kij"]),
+                              lattice=1), 0))
 
     def fresh(wl, prec):
         s = make(wl, prec, capi=capi)
@@ -126,25 +134,33 @@ def test_batched_multipass_members_bitwise():
             s.set_tuning(1, 0)     # D2Q9 on the multi-pass kernels
         return s
 
-    alone41, alone46 = [], []
+    marks = [41, 111, 181, 251, 256]
+    alone = []
     for wl, prec in wls:
         s = fresh(wl, prec)
-        s.step_n(41)
-        alone41.append(s.read_populations())
-        s.step_n(5)
-        alone46.append(s.read_populations())
+        done, refs = 0, []
+        for m in marks:
+            s.step_n(m - done)
+            done = m
+            refs.append(s.read_populations())
+        alone.append(refs)
         s.close()
     sims = [fresh(wl, prec) for wl, prec in wls]
     capi.step_many(sims, 17)
     capi.step_many(sims, 24)
-    for s, ref in zip(sims, alone41):
-        assert np.array_equal(s.read_populations(), ref)
+    for s, ref in zip(sims, alone):
+        assert np.array_equal(s.read_populations(), ref[0])
         assert s.diagnostics()["step"] == 41
+    for call in range(3):
+        capi.step_many(sims, 70)
+        for s, ref in zip(sims, alone):
+            assert np.array_equal(s.read_populations(), ref[1 + call])
     sims[2].close()
     rest = sims[:2] + sims[3:]
     capi.step_many(rest, 5)
-    for s, ref in zip(rest, alone46[:2] + alone46[3:]):
-        assert np.array_equal(s.read_populations(), ref)
+    for s, ref in zip(rest, alone[:2] + alone[3:]):
+        assert np.array_equal(s.read_populations(), ref[4])
+        assert s.diagnostics()["step"] == 256
     for s in rest:
         s.close()
 
