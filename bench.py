@@ -107,6 +107,28 @@ def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0, kernel=0, stea
     return res
 
 
+def copy_rate(mib=1024, reps=10):
+    """A plain device-to-device copy of `mib` MiB on this GPU (torch's copy,
+    hipMemcpyAsync underneath), GB/s counting the bytes read and written:
+    the machine's own read-plus-write reference beside the 8 TB/s peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
+    del a, b
+    return 2.0 * n * 8 * reps / t / 1e9
+
+
 def sweep_leg(steps=512, acc_steps=200000, acc_count=8):
     """Batched ternary sweep (256 C1/C3/nC10 instances, FP32 storage, one
     launch per step, graph-replayed) against the same instances stepped one
@@ -612,6 +634,9 @@ def main():
                 rows_per_item=r64["rows"])
     if "steady" in r64:
         roof["steady_state"] = r64["steady"]
+    copy_gbs = copy_rate()
+    roof["copy_gbs"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(r64["achieved_gbs"] / copy_gbs, 4)
     out = dict(metric="component-site updates/s & %HBM roofline; p50/p99 time-to-equilibrium",
                value=round(r64["csu"], 1),
                unit="CSU/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -628,6 +653,7 @@ def main():
                                  launch_ms=round(r32["launch_ms"], 5),
                                  frac_72B=round(72 * r32["csu_per_step"] / (r32["launch_ms"] * 1e-3)
                                                 / 1e9 / HBM_PEAK_GBS, 4),
+                                 frac_of_copy=round(r32["achieved_gbs"] / copy_gbs, 4),
                                  kernel=KERNEL_NAMES.get(r32["kernel"], "generic") % "float",
                                  rows_per_item=r32["rows"], steady_state=r32.get("steady")),
                status=[r64["status"], r32["status"]])
