@@ -502,6 +502,33 @@ def marker_summary(db_path):
         print("| `%s` | %d | %.2f | %.3f | %.3f |" % (name, len(d), sum(d), sum(d) / len(d), max(d)))
 
 
+def sq_summary(db_paths, kernel="k_fused_d2q9_ws"):
+    """Median per dispatch of every counter in the given rocprofv3 counter
+    databases (separate passes of one workload) for the kernels whose name
+    contains `kernel`, and the wavefront-cycle fractions derived from them.
+    Prints a markdown table."""
+    import sqlite3
+    import statistics
+    vals = {}
+    for path in db_paths:
+        db = sqlite3.connect(path)
+        for name, counter, value in db.execute(
+                "select kernel_name, counter_name, value from counters_collection"):
+            if kernel in name:
+                vals.setdefault(counter, []).append(value)
+    med = {c: statistics.median(v) for c, v in vals.items()}
+    print("| counter | median per dispatch |")
+    print("|---|---|")
+    for c in sorted(med):
+        print("| %s | %.0f |" % (c, med[c]))
+    wc = med.get("SQ_WAVE_CYCLES")
+    if wc:
+        for c in ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_SCA", "SQ_WAIT_ANY",
+                  "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS"):
+            if c in med:
+                print("| %s / SQ_WAVE_CYCLES | %.3f |" % (c, med[c] / wc))
+
+
 def _counter_values(db_path, counter):
     """(kernel name, value) of every dispatch in a rocprofv3 counter-collection
     database, in dispatch order."""
@@ -578,6 +605,9 @@ def main():
                     help="only summarise a rocprofv3 results database of a kernel-trace run "
                          "of this script (per-kernel durations; the last --steps dispatches "
                          "of each kernel are the timed window)")
+    ap.add_argument("--sq-summary", nargs="+", default=None,
+                    help="print the fused kernel's SQ counters (median per dispatch) from "
+                         "rocprofv3 counter databases and exit")
     ap.add_argument("--marker-summary", default=None,
                     help="print the library's roctx ranges from a rocprofv3 --marker-trace "
                          "results database and exit")
@@ -596,6 +626,9 @@ def main():
         return
     if args.marker_summary:
         marker_summary(args.marker_summary)
+        return
+    if args.sq_summary:
+        sq_summary(args.sq_summary)
         return
     if args.calib_copy_mib:
         import torch
