@@ -250,6 +250,11 @@ __device__ __forceinline__ void collide_push_tau1(const PopLayout<ST> &P, char *
         yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
         zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
         put_pop<L>((ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)), v);
+        // FP32: one direction at a time.  Left free, the scheduler computes
+        // all eighteen FP64 results before the first store and then sums
+        // their FP32 roundings (109 VGPRs, four wavefronts per SIMD); in
+        // order it needs 82 (five), which keeps more stores in flight
+        if constexpr (sizeof(ST) == 4) __builtin_amdgcn_sched_barrier(0);
     }
     double o0;
     if constexpr (sizeof(ST) == 4)
