@@ -337,14 +337,16 @@ def d3q19_leg(n=128, steps=100, warmup=10):
     return out
 
 
-def small_configs_leg(config1_steps=2000, window=200, sweep_window=2):
+def small_configs_leg(config1_steps=2000, config2_steps=20000, window=200, sweep_window=2):
     """The CPU-baseline plan for the smaller configurations: the oracle
     (all OpenMP threads and one thread) beside the GPU on
     * the 64^2 C1/C3/nC5 droplet (config 1): its full 2000 steps on the
-      GPU (FP64, cache-resident: reported as steps/s and CSU/s), the
-      oracle over a `window`-step sample;
-    * the 256 x 32 Table II slabs, N = 1..6 (config 2): the oracle over a
-      `window`-step sample per case (the GPU side is the time-vs-N leg);
+      GPU (FP64, cache-resident: reported as steps/s and CSU/s) and on the
+      oracle, with all threads and with one;
+    * the 256 x 32 Table II slabs, N = 1..6 (config 2): the oracle over
+      each case's full 20000 steps with all threads, and over a
+      `window`-step sample per case on one thread (the GPU side is the
+      time-vs-N leg);
     * the 256 ternary sweep instances (config 3): the oracle over
       `sweep_window` steps of every instance, one after another.
     Oracle rates are CSU/s over the stated samples."""
@@ -377,26 +379,42 @@ def small_configs_leg(config1_steps=2000, window=200, sweep_window=2):
         set_threads(nt)
         o = OracleLBM(om, 0, (64, 64), rho)
         t0 = time.perf_counter()
-        o.run(window)
-        rates[nt] = csu1 * window / (time.perf_counter() - t0)
+        o.run(config1_steps)
+        rates[nt] = csu1 * config1_steps / (time.perf_counter() - t0)
+        print("small_configs: oracle, droplet, %d steps on %d thread(s)" % (config1_steps, nt),
+              file=sys.stderr, flush=True)
     out["config1_droplet64"] = dict(
         gpu=dict(steps=config1_steps, steps_per_s=round(config1_steps / g, 1),
                  csu_s=round(csu1 * config1_steps / g, 1)),
-        oracle=dict(sample="%d steps" % window, csu_s_all_cores=round(rates[threads], 1),
+        oracle=dict(sample="%d steps (the full run)" % config1_steps,
+                    csu_s_all_cores=round(rates[threads], 1),
                     csu_s_one_thread=round(rates[1], 1)))
     # config 2
-    c2 = []
-    set_threads(threads)
+    c2, c2_1, c2_wall = [], [], []
     for case in range(1, 7):
         comps, T, _ = C.table_ii_components(case)
         v = S["vle%d" % case]
-        o = OracleLBM(oracle_mixture(comps, T), 0, (256, 32),
-                      Fi.slab(256, 32, v["rho_V"], v["rho_L"], 0.5))
+        rho2 = Fi.slab(256, 32, v["rho_V"], v["rho_L"], 0.5)
+        csu2 = len(comps) * 256 * 32
+        set_threads(threads)
+        o = OracleLBM(oracle_mixture(comps, T), 0, (256, 32), rho2)
+        t0 = time.perf_counter()
+        o.run(config2_steps)
+        dt = time.perf_counter() - t0
+        c2.append(round(csu2 * config2_steps / dt, 1))
+        c2_wall.append(round(dt, 2))
+        print("small_configs: oracle, Table II case %d, %d steps in %.1f s"
+              % (case, config2_steps, dt), file=sys.stderr, flush=True)
+        set_threads(1)
+        o = OracleLBM(oracle_mixture(comps, T), 0, (256, 32), rho2)
         t0 = time.perf_counter()
         o.run(window)
-        c2.append(round(len(comps) * 256 * 32 * window / (time.perf_counter() - t0), 1))
-    out["config2_vle_256x32"] = dict(N=[1, 2, 3, 4, 5, 6], oracle_csu_s_all_cores=c2,
-                                     sample="%d steps per case" % window)
+        c2_1.append(round(csu2 * window / (time.perf_counter() - t0), 1))
+    set_threads(threads)
+    out["config2_vle_256x32"] = dict(
+        N=[1, 2, 3, 4, 5, 6], oracle_csu_s_all_cores=c2, oracle_wall_s_all_cores=c2_wall,
+        sample_all_cores="%d steps per case (the full run)" % config2_steps,
+        oracle_csu_s_one_thread=c2_1, sample_one_thread="%d steps per case" % window)
     # config 3
     from paper_2306_10652_amd import batch
     specs = batch.ternary_specs(S["ternary_sweep"])
