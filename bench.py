@@ -197,16 +197,28 @@ def sweep_leg(steps=512, acc_steps=200000, acc_count=8):
                                               max_abs_mole_fraction=ex))
 
 
-def time_vs_n_leg(steps=2000):
+def _linear_fit(x, y):
+    A = np.vstack([x, np.ones(len(x))]).T
+    coef, *_ = np.linalg.lstsq(A, np.array(y), rcond=None)
+    fit = A @ coef
+    y = np.array(y)
+    return coef, 1 - np.sum((y - fit) ** 2) / np.sum((y - np.mean(y)) ** 2)
+
+
+def time_vs_n_leg(steps=2000, big=1024, big_steps=200):
     """Per-step time against component count: Table II cases 1-6 as
     256 x 32 flat slabs, FP64 (the paper reports linear growth in N), and
-    the same with FP32 storage."""
+    the same with FP32 storage (wall time over `steps` steps).  These grids
+    sit in the caches and the step is bound by latency, which grows with
+    the wavefronts per SIMD of the fused kernel's N + 2 wavefronts rather
+    than with N itself; the same slabs at big x big, where the step streams
+    its populations from HBM, are timed too (HIP events over `big_steps`)."""
     import torch
     from paper_2306_10652_amd import capi
     from inputs import components as C
     from inputs import fields as Fi
     S = Fi.load_phase_states()
-    Ns, us, us32 = [], [], []
+    Ns, us, us32, usb, usb32 = [], [], [], [], []
     st = torch.cuda.Stream()
     for case in range(1, 7):
         comps, T, _ = C.table_ii_components(case)
@@ -222,14 +234,31 @@ def time_vs_n_leg(steps=2000):
             torch.cuda.synchronize()
             out.append((time.perf_counter() - t0) / steps * 1e6)
             sim.close()
+        rho = Fi.slab(big, big, v["rho_V"], v["rho_L"], 0.5)
+        for prec, out in ((capi.FP64, usb), (capi.FP32_STORAGE, usb32)):
+            sim = capi.Simulation(mix, capi.D2Q9, prec, (big, big), rho, stream=st)
+            sim.step_n(64)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            sim.step_n(big_steps)
+            e1.record(st)
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1) / big_steps * 1e3)
+            sim.close()
         Ns.append(len(comps))
-    A = np.vstack([Ns, np.ones(len(Ns))]).T
-    coef, *_ = np.linalg.lstsq(A, np.array(us), rcond=None)
-    fit = A @ coef
-    r2 = 1 - np.sum((np.array(us) - fit) ** 2) / np.sum((np.array(us) - np.mean(us)) ** 2)
+    coef, r2 = _linear_fit(Ns, us)
+    coefb, r2b = _linear_fit(Ns, usb)
+    coefb32, r2b32 = _linear_fit(Ns, usb32)
     return dict(grid=[256, 32], N=Ns, us_per_step=[round(u, 2) for u in us],
                 slope_us_per_component=round(coef[0], 3), r2=round(float(r2), 4),
-                us_per_step_fp32_storage=[round(u, 2) for u in us32])
+                us_per_step_fp32_storage=[round(u, 2) for u in us32],
+                hbm_bound=dict(grid=[big, big], steps=big_steps,
+                               us_per_step=[round(u, 2) for u in usb],
+                               slope_us_per_component=round(coefb[0], 3), r2=round(float(r2b), 4),
+                               us_per_step_fp32_storage=[round(u, 2) for u in usb32],
+                               r2_fp32_storage=round(float(r2b32), 4)))
 
 
 def serving_leg(count=10, load=0.8, tol=1e-8, max_steps=200000, max_n2d=None, max_n3d=None,
