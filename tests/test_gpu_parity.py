@@ -294,6 +294,47 @@ def test_d3q19_largest_serving_size(precision):
     assert e <= (1e-12 if precision == 0 else 1e-6)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_grid_at_the_32bit_offset_limit(precision):
+    """The largest grids: 14720 x 14720 with two components.  Its
+    population buffer holds 3.9e9 elements in FP64, 91 % of the range of
+    the fused kernels' 32-bit per-buffer offsets (the fused path), and
+    4.33e9 with FP32 storage, past 2^32, which sends it to the multi-pass
+    kernels and their 64-bit offsets.  The initial field repeats one seeded
+    64 x 64 droplet tile (with noise), so every later state is 64-periodic
+    too: after 5 steps every site must equal the oracle's 64 x 64 run at
+    (x mod 64, y mod 64) (FP64 <= 1e-12, FP32 storage <= 1e-6)."""
+    import torch
+    capi = _capi()
+    t, k = 64, 230
+    n = t * k
+    wl = W.random_droplet(2, (t, t), seed=2024)
+    o = wl.oracle()
+    assert o.run(5) == 0
+    ref = o.rho().reshape(2, t, t)
+    mix = wl.gpu_mixture()
+    rho = np.tile(np.asarray(wl.rho).reshape(2, 1, t, t), (1, 1, k, k))
+    nbytes = capi.fields_bytes(2, 0, precision, n, n, 1)
+    sim = capi.Simulation(mix, 0, precision, (n, n), rho)
+    del rho
+    sim.step_n(5)
+    kernel = sim.info()["kernel"]
+    out = sim.read_moments(velocity=False)
+    g = out["rho"].reshape(2, k, t, k, t)
+    e = float(np.max(np.abs(g - ref[:, None, :, None, :]) / ref[:, None, :, None, :]))
+    report("grid_32bit_limit", n=n, precision=precision, kernel=kernel, fields_bytes=nbytes,
+           rho_rel=e)
+    sim.close()
+    mix.close()
+    del g
+    torch.cuda.empty_cache()
+    assert out["status"] == 0
+    # FP64: a fused variant (2 or 3); FP32 storage, past 2^32 elements per
+    # buffer: the multi-pass kernels (1)
+    assert kernel in ((2, 3) if precision == 0 else (1,))
+    assert e <= (1e-12 if precision == 0 else 1e-6)
+
+
 def test_spinodal10_full_size_window_fp64():
     """1024 x 1024, ten components, seeded kij: the fused kernel in its
     benchmark launch configuration (variant and rows as the autotuner picks
