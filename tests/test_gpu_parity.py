@@ -294,44 +294,49 @@ def test_d3q19_largest_serving_size(precision):
     assert e <= (1e-12 if precision == 0 else 1e-6)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_grid_at_the_32bit_offset_limit(precision):
-    """The largest grids: 14720 x 14720 with two components.  Its
+@pytest.mark.parametrize("lattice,precision,t,k", [(0, 0, 64, 230), (0, 1, 64, 230),
+                                                   (1, 0, 44, 11)])
+def test_grid_at_the_32bit_offset_limit(lattice, precision, t, k):
+    """The largest grids.  D2Q9 14720 x 14720 with two components: its
     population buffer holds 3.9e9 elements in FP64, 91 % of the range of
     the fused kernels' 32-bit per-buffer offsets (the fused path), and
     4.33e9 with FP32 storage, past 2^32, which sends it to the multi-pass
-    kernels and their 64-bit offsets.  The initial field repeats one seeded
-    64 x 64 droplet tile (with noise), so every later state is 64-periodic
-    too: after 5 steps every site must equal the oracle's 64 x 64 run at
-    (x mod 64, y mod 64) (FP64 <= 1e-12, FP32 storage <= 1e-6)."""
+    kernels and their 64-bit offsets.  D3Q19 484^3 with two components,
+    FP64: 4.56e9 elements (multi-pass).  The initial field repeats one
+    seeded t^D droplet tile (with noise), so every later state is periodic
+    with period t too: after 5 steps every site must equal the oracle's t^D
+    run at (x mod t, y mod t, z mod t) (FP64 <= 1e-12, FP32 storage
+    <= 1e-6)."""
     import torch
     capi = _capi()
-    t, k = 64, 230
     n = t * k
-    wl = W.random_droplet(2, (t, t), seed=2024)
+    D = 2 if lattice == 0 else 3
+    wl = W.random_droplet(2, (t,) * D, seed=2024, lattice=lattice)
     o = wl.oracle()
     assert o.run(5) == 0
-    ref = o.rho().reshape(2, t, t)
+    nz = k if lattice else 1
+    tz = t if lattice else 1
+    ref = o.rho().reshape(2, 1, tz, 1, t, 1, t)
     mix = wl.gpu_mixture()
-    rho = np.tile(np.asarray(wl.rho).reshape(2, 1, t, t), (1, 1, k, k))
-    nbytes = capi.fields_bytes(2, 0, precision, n, n, 1)
-    sim = capi.Simulation(mix, 0, precision, (n, n), rho)
+    rho = np.tile(np.asarray(wl.rho).reshape(2, tz, t, t), (1, nz, k, k))
+    nbytes = capi.fields_bytes(2, lattice, precision, n, n, n if lattice else 1)
+    sim = capi.Simulation(mix, lattice, precision, (n,) * D, rho)
     del rho
     sim.step_n(5)
     kernel = sim.info()["kernel"]
     out = sim.read_moments(velocity=False)
-    g = out["rho"].reshape(2, k, t, k, t)
-    e = float(np.max(np.abs(g - ref[:, None, :, None, :]) / ref[:, None, :, None, :]))
-    report("grid_32bit_limit", n=n, precision=precision, kernel=kernel, fields_bytes=nbytes,
-           rho_rel=e)
+    g = out["rho"].reshape(2, nz, tz, k, t, k, t)
+    e = float(np.max(np.abs(g - ref) / ref))
+    report("grid_32bit_limit", lattice=lattice, n=n, precision=precision, kernel=kernel,
+           fields_bytes=nbytes, rho_rel=e)
     sim.close()
     mix.close()
     del g
     torch.cuda.empty_cache()
     assert out["status"] == 0
-    # FP64: a fused variant (2 or 3); FP32 storage, past 2^32 elements per
-    # buffer: the multi-pass kernels (1)
-    assert kernel in ((2, 3) if precision == 0 else (1,))
+    # D2Q9 FP64: a fused variant (2 or 3); past 2^32 elements per buffer:
+    # the multi-pass kernels (1)
+    assert kernel in ((2, 3) if (lattice, precision) == (0, 0) else (1,))
     assert e <= (1e-12 if precision == 0 else 1e-6)
 
 
