@@ -27,6 +27,15 @@
  *    never keeps a caller's host pointer.
  *  - A mixture must outlive every simulation made from it.  Handles are not
  *    thread-safe: use one handle from one thread at a time.
+ *  - Streams: fuglbm_step_n and fuglbm_step_many may be called on a
+ *    simulation with a different hip_stream than its previous call; the
+ *    new launches then wait, on the device, for the simulation's earlier
+ *    work (an event the library records after each such call), with no host
+ *    synchronisation.  The synchronising calls (read_moments, diagnostics,
+ *    read/write_populations, set_tuning, destroy_sim) run on and wait for
+ *    the stream of the simulation's last enqueuing call, which must still
+ *    exist then.  fuglbm_step_many_noalloc does not order across streams
+ *    (see there).
  *  - Device populations (two buffers swapped every step): with FP64
  *    storage they are blocked by lattice row (row = y + ny*z): row r holds
  *    the rest populations g_{0,i} of all components as [ncomp][pitch]
@@ -196,7 +205,10 @@ fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count, int64_t n
  * fused variant and rows per work item).
  * Limits: at most 256 simulations and 65536 fused work items per call
  * (EINVAL beyond); every member must be a D2Q9 simulation on a fused
- * kernel (EINVAL otherwise).  Members with a sticky device error are
+ * kernel (EINVAL otherwise).  No stream ordering: a member's earlier work
+ * on another stream must be complete or ordered before hip_stream by the
+ * caller, and so must this call's launches before a later call on another
+ * stream.  Members with a sticky device error are
  * skipped and ENONFINITE is returned after the others have been stepped.
  * Every call on one GPU shares the array: calls that overlap on one GPU
  * (other streams or threads before this call's launches have finished)

@@ -223,9 +223,29 @@ struct fuglbm_sim {
     bool have_snap;
     uint32_t sticky;
     hipStream_t last_stream;
+    // recorded on last_stream after each enqueuing call: a call on another
+    // stream waits for it on the device (done_valid: the record is current)
+    hipEvent_t done;
+    bool done_valid;
     GraphCache graph;
     uint64_t uid;          // never reused; batch tables key on it, not on the address
 };
+
+// Work about to be enqueued on st waits (on the device) for the
+// simulation's earlier work on another stream: its own event, so no
+// reference to that stream is kept.
+static fuglbm_status order_after(fuglbm_sim *s, hipStream_t st) {
+    if (s->done_valid && s->last_stream != st) HIP_TRY(hipStreamWaitEvent(st, s->done, 0));
+    s->last_stream = st;
+    return FUGLBM_OK;
+}
+
+static fuglbm_status mark_done(fuglbm_sim *s, hipStream_t st) {
+    HIP_TRY(hipEventRecord(s->done, st));
+    s->done_valid = true;
+    s->last_stream = st;
+    return FUGLBM_OK;
+}
 
 static int64_t pop_bytes(const fuglbm_sim *s) {
     const int64_t rows = (int64_t)s->ny * s->nz;
@@ -693,6 +713,12 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     s->fsim = (FusedSim *)(s->base + s->cv.fsim);
     s->items = (FusedItem *)(s->base + s->cv.items);
     s->parity = 0;
+    if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) {
+        if (s->owned) (void)hipFree(s->base);
+        delete s;
+        return fail(FUGLBM_EDEVICE, "hipEventCreate");
+    }
+    s->done_valid = false;
     // constant block
     SimConst &c = s->hc;
     std::memset(&c, 0, sizeof(c));
@@ -721,6 +747,7 @@ fuglbm_status fuglbm_init_fields(const fuglbm_mixture *mix, fuglbm_lattice latti
     }
     fuglbm_status rc = FUGLBM_OK;
     auto bail = [&](fuglbm_status r) {
+        (void)hipEventDestroy(s->done);
         if (s->owned) (void)hipFree(s->base);
         delete s;
         return r;
@@ -816,7 +843,10 @@ fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
     if (nsteps < 0) return fail(FUGLBM_EINVAL, "nsteps must be >= 0");
     if (s->sticky) return fail(FUGLBM_ENONFINITE, "simulation has a sticky device error");
     hipStream_t st = (hipStream_t)hip_stream;
-    s->last_stream = st;
+    {
+        fuglbm_status rc = order_after(s, st);
+        if (rc != FUGLBM_OK) return rc;
+    }
     int64_t left = nsteps;
     if (left > 0 && is_fused(s->kernel) && s->autotune && !s->tuned) {
         fuglbm_status rc = autotune_rows(s, st);
@@ -845,7 +875,7 @@ fuglbm_status fuglbm_step_n(fuglbm_sim *s, int64_t nsteps, void *hip_stream) {
         s->parity ^= 1;
         ++s->step;
     }
-    return FUGLBM_OK;
+    return mark_done(s, st);
 }
 
 fuglbm_status fuglbm_read_moments(fuglbm_sim *s, double *rho_out, double *u_out,
@@ -1016,6 +1046,7 @@ void fuglbm_destroy_sim(fuglbm_sim *s) {
     (void)hipStreamSynchronize(s->last_stream);
     forget_sim_in_batches(s);
     drop_graph(s);
+    if (s->done) (void)hipEventDestroy(s->done);
     if (s->owned) (void)hipFree(s->base);
     delete s;
 }
@@ -1348,6 +1379,11 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
         else
             others.push_back(s);
     }
+    for (int k = 0; k < count; ++k) {
+        if (sims[k]->sticky) continue;
+        fuglbm_status rc = order_after(sims[k], st);
+        if (rc != FUGLBM_OK) return rc;
+    }
     for (auto &kv : groups) {
         auto &group = kv.second;
         BatchTable &bt = batch_tables()[kv.first];
@@ -1457,6 +1493,11 @@ extern "C" fuglbm_status fuglbm_step_many(fuglbm_sim *const *sims, int32_t count
             s->step += nsteps;
             s->last_stream = st;
         }
+    }
+    for (int k = 0; k < count; ++k) {
+        if (sims[k]->sticky) continue;
+        fuglbm_status rc = mark_done(sims[k], st);
+        if (rc != FUGLBM_OK) return rc;
     }
     if (skipped) return fail(FUGLBM_ENONFINITE, "some simulations have a sticky device error");
     return FUGLBM_OK;
@@ -1663,6 +1704,7 @@ extern "C" fuglbm_status fuglbm_step_many_noalloc(fuglbm_sim *const *sims, int32
         s->parity ^= (int)(nsteps & 1);
         s->step += nsteps;
         s->last_stream = st;
+        s->done_valid = false;   // not recorded here (the caller orders streams)
     }
     if (skipped) return fail(FUGLBM_ENONFINITE, "some simulations have a sticky device error");
     return FUGLBM_OK;

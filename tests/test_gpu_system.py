@@ -68,6 +68,40 @@ def test_bitwise_determinism_and_batched_equals_single():
         assert np.array_equal(s.read_populations(), ref)
 
 
+def test_calls_on_different_streams_are_ordered():
+    """Calls on one simulation from different streams, with no host
+    synchronisation between them (step_n, then step_many, on streams a and
+    b in turn; long enough that unordered launches would overlap): each
+    call waits on the device for the simulation's earlier work on the other
+    stream, so the state is bitwise that of the same steps on one stream.
+    D2Q9 (fused) and D3Q19 (multi-pass) members."""
+    import torch
+    capi = _capi()
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    wls = [W.random_droplet(3, (512, 384), seed=71),
+           W.random_droplet(2, (48, 40, 36), seed=72, lattice=1)]
+    plan = [(a, 300), (b, 1), (a, 65), (b, 200)]
+    total = sum(n for _, n in plan)
+    refs = []
+    for wl in wls:
+        s = make(wl, capi=capi)
+        s.step_n(total)
+        refs.append(s.read_populations())
+        s.close()
+    for wl, ref in zip(wls, refs):
+        s = make(wl, capi=capi)
+        for st, n in plan:
+            s.step_n(n, st)
+        assert np.array_equal(s.read_populations(), ref)
+        s.close()
+    sims = [make(wl, capi=capi) for wl in wls]
+    for st, n in plan:
+        capi.step_many(sims, n, st)
+    for s, ref in zip(sims, refs):
+        assert np.array_equal(s.read_populations(), ref)
+        s.close()
+
+
 def test_heterogeneous_batch_and_degenerate_calls():
     """One step_many call over simulations that differ in component count,
     precision and lattice (grouped into one launch per (N, precision) for
