@@ -34,6 +34,11 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2306_10652_amd", "csrc", f)
 KERNEL_NAMES = {2: "k_fused_d2q9<10,%s>", 3: "k_fused_d2q9_ws<10,%s>"}
 
 
+def kernel_name(kernel, st):
+    """Name of the step kernel the library ran (storage type st)."""
+    return KERNEL_NAMES[kernel] % st if kernel in KERNEL_NAMES else "multi-pass (generic)"
+
+
 def kernel_hash():
     """Hash of the fused kernels' sources (the profile summary records the
     hash it was measured with; a changed kernel voids its traffic figure)."""
@@ -64,7 +69,7 @@ def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0, kernel=0, stea
     info = sim.info()
     sim.step_n(warmup)                  # the first call autotunes rows (not timed)
     tuning = sim.get_tuning()
-    sim.diagnostics()
+    mass0 = np.array(sim.diagnostics()["mass"], dtype=float)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -91,7 +96,8 @@ def time_gpu(precision, steps, warmup, n, diag_every=100, rows=0, kernel=0, stea
     res = dict(csu=csu, csu_per_step=N * n * n, wall=wall, ms_per_step=wall * 1e3 / steps,
                launch_ms=launch_s * 1e3, alg_bytes=alg, achieved_gbs=alg / launch_s / 1e9, kernel=tuning["kernel"],
                rows=tuning["rows"],
-               status=d["status"], residual=d["residual"], mass=d["mass"].tolist())
+               status=d["status"], residual=d["residual"], mass=d["mass"].tolist(),
+               mass_drift=float(np.max(np.abs(np.array(d["mass"], dtype=float) - mass0) / mass0)))
     if steady_steps:
         # after the timed window: a longer run on the same simulation, for
         # the rate once the GPU's clocks have settled under sustained load,
@@ -473,9 +479,12 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(n, budget_s=15.0):
+def cpu_baseline(n, budget_s=15.0, gpu_check=True):
     """The CPU oracle on a bounded sample: whole 1024^2 steps until ~budget
-    with every thread OpenMP gets, then one step on one thread."""
+    with every thread OpenMP gets, then one step on one thread.  The
+    sample's end state also checks the GPU (gpu_check): the same input
+    stepped as many times by the library (FP64, its benchmark launch
+    configuration), densities compared over the whole field."""
     from oracle.lbm import OracleLBM, oracle_mixture, build_oracle, set_threads
     build_oracle()
     comps, T, kij, rho = build_inputs(n)
@@ -490,6 +499,18 @@ def cpu_baseline(n, budget_s=15.0):
         if time.perf_counter() - t0 > budget_s or k >= 20:
             break
     dt = time.perf_counter() - t0
+    parity = None
+    if gpu_check:
+        from paper_2306_10652_amd import capi
+        mix = capi.Mixture.from_components(comps, T, kij, kappa_ref=0.02, tau=1.0)
+        sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (n, n), rho)
+        sim.step_n(k)
+        g = sim.read_moments(velocity=False)["rho"]
+        ref = o.rho()
+        parity = dict(steps=k, rho_max_rel=float(np.max(np.abs(g - ref) / ref)),
+                      kernel=kernel_name(sim.info()["kernel"], "double"))
+        sim.close()
+        mix.close()
     set_threads(1)
     t1 = time.perf_counter()
     o.run(1)
@@ -501,6 +522,7 @@ def cpu_baseline(n, budget_s=15.0):
                        % (k, n, n, dt),
                 one_thread=dict(value=csu / dt1, unit="CSU/s",
                                 sample="1 full step on 1 thread, %.1f s" % dt1),
+                gpu_vs_oracle=parity,
                 nproc=os.cpu_count(), cpu_model=cpu_model())
 
 
@@ -721,7 +743,7 @@ def main():
                 unit="GB/s", frac=round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4),
                 traffic=traffic, alg_bytes_per_launch=r64["alg_bytes"],
                 launch_ms=round(r64["launch_ms"], 5),
-                kernel=KERNEL_NAMES.get(r64["kernel"], "generic") % "double",
+                kernel=kernel_name(r64["kernel"], "double"),
                 rows_per_item=r64["rows"])
     if "steady" in r64:
         roof["steady_state"] = r64["steady"]
@@ -745,9 +767,10 @@ def main():
                                  frac_72B=round(72 * r32["csu_per_step"] / (r32["launch_ms"] * 1e-3)
                                                 / 1e9 / HBM_PEAK_GBS, 4),
                                  frac_of_copy=round(r32["achieved_gbs"] / copy_gbs, 4),
-                                 kernel=KERNEL_NAMES.get(r32["kernel"], "generic") % "float",
+                                 kernel=kernel_name(r32["kernel"], "float"),
                                  rows_per_item=r32["rows"], steady_state=r32.get("steady")),
-               status=[r64["status"], r32["status"]])
+               status=[r64["status"], r32["status"]],
+               mass_drift=[r64["mass_drift"], r32["mass_drift"]])
     legs = set() if args.no_extra else set(args.legs.split(","))
     if "sweep" in legs:
         out["batched_sweep"] = sweep_leg()
