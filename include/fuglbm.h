@@ -46,10 +46,10 @@
  *    rest population is stored as rho_i minus the FP64 sum of the site's
  *    stored moving populations, so component masses are conserved to FP64
  *    rounding (Eq. (1a)-(1c) conserve each component's mass); the fused
- *    D2Q9 kernels collide the moving populations in FP32 arithmetic, the
- *    multi-pass kernels in FP64 (at tau != 1 the multi-pass
- *    collision instead folds the moving populations' rounding error into
- *    the rest population).  Moments, the EOS, psi_i and the gradients are
+ *    D2Q9 kernels and the multi-pass kernels at tau == 1 collide the
+ *    moving populations in FP32 arithmetic (at tau != 1 the multi-pass
+ *    collision runs in FP64 and folds the moving populations' rounding
+ *    error into the rest population).  Moments, the EOS, psi_i and the gradients are
  *    FP64 in both precisions.  Host-side population arrays
  *    (read/write_populations) are [ncomp][Q][sites] FP64, site = x +
  *    nx*(y + ny*z).

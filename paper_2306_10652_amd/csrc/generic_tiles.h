@@ -198,12 +198,15 @@ __device__ __forceinline__ void put_pop(T *p, T v) {
 // (weight classes |e|^2 = 1 and 2); the dot products with e_a add only its
 // non-zero components (0 * u is not folded away).  The moving populations
 // are pushed to x + e_a (periodic; in y and z only where pop_col says so),
-// the rest one stays.  In FP32 storage
-// the rest population is rho minus the FP64 sum of the stored moving
-// values (in direction order): the collision conserves each component's
-// mass, so this keeps it to FP64 rounding, and the sum needs only the
-// stored values (summing each direction's rounding error instead keeps all
-// eighteen FP64 values live until the end).
+// the rest one stays.  In FP32 storage the moving populations are computed
+// in FP32 arithmetic from the per-site terms rounded once (as in the fused
+// D2Q9 kernels), and the rest population is rho minus the FP64 sum of the
+// stored moving values (in direction order): the collision conserves each
+// component's mass, so this keeps it to FP64 rounding.  The FP32 loop
+// stores each direction before computing the next (a scheduling barrier):
+// left free, the compiler computes every direction first and holds them
+// all (109 VGPRs with FP64 arithmetic; 63 in order with FP32 arithmetic,
+// eight wavefronts per SIMD).
 template <class L, typename ST>
 __device__ __forceinline__ void collide_push_tau1(const PopLayout<ST> &P, char *gdb, int i, int x,
                                                   int y, int z, int nx, int ny, int nz, double r,
@@ -219,50 +222,63 @@ __device__ __forceinline__ void collide_push_tau1(const PopLayout<ST> &P, char *
     const double uu = ux * ux + uy * uy + uz * uz;
     const double Fu = Fx * ux + Fy * uy + Fz * uz;
     const double Gu = Gx * ux + Gy * uy + Gz * uz;
-    double msum = 0.0;
     const double c0 = -1.5 * uu;
     const double K1 = -3.0 * Fu - Gu + 0.5 * (3.0 - (double)L::D) * Gu;
     const double K2 = -3.0 * Fu - Gu + 0.5 * (6.0 - (double)L::D) * Gu;
     const double A1 = omega * L::w(1) * r, A2 = omega * L::w(L::Q - 1) * r;
     const double B1 = fcoef * L::w(1), B2 = fcoef * L::w(L::Q - 1);
-    auto edot = [](int a, double ex, double ey, double ez) {
+    auto edot = [](int a, auto ex, auto ey, auto ez) {
         const int cx = L::ex(a), cy = L::ey(a), cz = L::ez(a);
-        const double tx = cx > 0 ? ex : -ex, ty = cy > 0 ? ey : -ey, tz = cz > 0 ? ez : -ez;
+        const auto tx = cx > 0 ? ex : -ex, ty = cy > 0 ? ey : -ey, tz = cz > 0 ? ez : -ez;
         if (cx != 0) return cy != 0 ? tx + ty : (cz != 0 ? tx + tz : tx);
         return cy != 0 ? (cz != 0 ? ty + tz : ty) : tz;
     };
-    // no loads: unrolled, the lattice vectors, weights and destination rows
-    // fold to constants per direction
-#pragma unroll
-    for (int a = 1; a < L::Q; ++a) {
-        const double eu = edot(a, ux, uy, uz);
-        const double eF = edot(a, Fx, Fy, Fz);
-        const double eG = edot(a, Gx, Gy, Gz);
-        const bool e1 = L::ex(a) * L::ex(a) + L::ey(a) * L::ey(a) + L::ez(a) * L::ez(a) == 1;
-        const double sq = fma(eu, fma(4.5, eu, 3.0), c0);
-        const double q = fma(eF, fma(9.0, eu, 3.0), fma(3.0 * eu, eG, e1 ? K1 : K2));
-        const double o = fma(e1 ? A1 : A2, sq, (e1 ? B1 : B2) * q);
-        const ST v = (ST)o;
-        if (sizeof(ST) == 4) msum += (double)v;
-        // push; in x only where the layout does (pop_col)
+    // push; in x only where the layout does (pop_col)
+    auto store = [&](int a, ST v) {
         int xx = L::PULL_X ? x : x + L::ex(a), yy = y + L::ey(a), zz = z + L::ez(a);
         xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
         yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
         zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
         put_pop<L>((ST *)(gdb + P.move((int64_t)yy + (int64_t)ny * zz, i, a, xx)), v);
-        // FP32: one direction at a time.  Left free, the scheduler computes
-        // all eighteen FP64 results before the first store and then sums
-        // their FP32 roundings (109 VGPRs, four wavefronts per SIMD); in
-        // order it needs 82 (five), which keeps more stores in flight
-        if constexpr (sizeof(ST) == 4) __builtin_amdgcn_sched_barrier(0);
+    };
+    // no loads: unrolled, the lattice vectors, weights and destination rows
+    // fold to constants per direction
+    if constexpr (sizeof(ST) == 4) {
+        const float fux = (float)ux, fuy = (float)uy, fuz = (float)uz;
+        const float fFx = (float)Fx, fFy = (float)Fy, fFz = (float)Fz;
+        const float fGx = (float)Gx, fGy = (float)Gy, fGz = (float)Gz;
+        const float fc0 = (float)c0, fK1 = (float)K1, fK2 = (float)K2;
+        const float fA1 = (float)A1, fA2 = (float)A2, fB1 = (float)B1, fB2 = (float)B2;
+        double msum = 0.0;
+#pragma unroll
+        for (int a = 1; a < L::Q; ++a) {
+            const float eu = edot(a, fux, fuy, fuz);
+            const float eF = edot(a, fFx, fFy, fFz);
+            const float eG = edot(a, fGx, fGy, fGz);
+            const bool e1 = L::ex(a) * L::ex(a) + L::ey(a) * L::ey(a) + L::ez(a) * L::ez(a) == 1;
+            const float sq = fmaf(eu, fmaf(4.5f, eu, 3.0f), fc0);
+            const float q = fmaf(eF, fmaf(9.0f, eu, 3.0f), fmaf(3.0f * eu, eG, e1 ? fK1 : fK2));
+            const float v = fmaf(e1 ? fA1 : fA2, sq, (e1 ? fB1 : fB2) * q);
+            msum += (double)v;
+            store(a, (ST)v);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        put_pop<L>((double *)(gdb + P.rest((int64_t)y + (int64_t)ny * z, i, x)), r - msum);
+    } else {
+#pragma unroll
+        for (int a = 1; a < L::Q; ++a) {
+            const double eu = edot(a, ux, uy, uz);
+            const double eF = edot(a, Fx, Fy, Fz);
+            const double eG = edot(a, Gx, Gy, Gz);
+            const bool e1 = L::ex(a) * L::ex(a) + L::ey(a) * L::ey(a) + L::ez(a) * L::ez(a) == 1;
+            const double sq = fma(eu, fma(4.5, eu, 3.0), c0);
+            const double q = fma(eF, fma(9.0, eu, 3.0), fma(3.0 * eu, eG, e1 ? K1 : K2));
+            store(a, (ST)fma(e1 ? A1 : A2, sq, (e1 ? B1 : B2) * q));
+        }
+        put_pop<L>((double *)(gdb + P.rest((int64_t)y + (int64_t)ny * z, i, x)),
+                   collide_one<L>(0, 0.0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu, omega,
+                                  fcoef));
     }
-    double o0;
-    if constexpr (sizeof(ST) == 4)
-        o0 = r - msum;
-    else
-        o0 = collide_one<L>(0, 0.0, r, ux, uy, uz, Fx, Fy, Fz, Gx, Gy, Gz, uu, Fu, Gu, omega,
-                            fcoef);
-    put_pop<L>((double *)(gdb + P.rest((int64_t)y + (int64_t)ny * z, i, x)), o0);
 }
 
 // Collision of component i at one site at tau != 1 (Eq. (1a)-(1c)): reads
