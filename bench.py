@@ -372,18 +372,17 @@ def d3q19_leg(n=128, steps=100, warmup=10):
     return out
 
 
-def small_configs_leg(config1_steps=2000, config2_steps=20000, window=200, sweep_window=2):
-    """The CPU-baseline plan for the smaller configurations: the oracle
-    (all OpenMP threads and one thread) beside the GPU on
-    * the 64^2 C1/C3/nC5 droplet (config 1): its full 2000 steps on the
-      GPU (FP64, cache-resident: reported as steps/s and CSU/s) and on the
-      oracle, with all threads and with one;
-    * the 256 x 32 Table II slabs, N = 1..6 (config 2): the oracle over
-      each case's full 20000 steps with all threads, and over a
-      `window`-step sample per case on one thread (the GPU side is the
-      time-vs-N leg);
-    * the 256 ternary sweep instances (config 3): the oracle over
-      `sweep_window` steps of every instance, one after another.
+def small_workloads_leg(droplet_steps=2000, slab_steps=20000, window=200, sweep_window=2):
+    """The oracle (all OpenMP threads and one thread) beside the GPU on the
+    smaller workloads:
+    * the 64^2 C1/C3/nC5 droplet: its full 2000 steps on the GPU (FP64,
+      cache-resident: reported as steps/s and CSU/s) and on the oracle,
+      with all threads and with one;
+    * the 256 x 32 Table II slabs, N = 1..6: the oracle over each case's
+      full 20000 steps with all threads, and over a `window`-step sample
+      per case on one thread (the GPU side is the time-vs-N leg);
+    * the 256 ternary sweep instances: the oracle over `sweep_window`
+      steps of every instance, one after another.
     Oracle rates are CSU/s over the stated samples."""
     import torch
     from paper_2306_10652_amd import capi
@@ -394,7 +393,7 @@ def small_configs_leg(config1_steps=2000, config2_steps=20000, window=200, sweep
     S = Fi.load_phase_states()
     threads = set_threads(0)
     out = dict(cores=threads, cpu_model=cpu_model())
-    # config 1
+    # the 64^2 droplet
     st = S["droplet3"]
     rho = Fi.add_noise(Fi.droplet(64, 64, st["rho_L"], st["rho_V"], 16.0), 1e-3, 1)
     mix = capi.Mixture.from_components(C.DROPLET_3, 250.0)
@@ -403,7 +402,7 @@ def small_configs_leg(config1_steps=2000, config2_steps=20000, window=200, sweep
     sim.step_n(100)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step_n(config1_steps)
+    sim.step_n(droplet_steps)
     torch.cuda.synchronize()
     g = time.perf_counter() - t0
     sim.close()
@@ -414,17 +413,17 @@ def small_configs_leg(config1_steps=2000, config2_steps=20000, window=200, sweep
         set_threads(nt)
         o = OracleLBM(om, 0, (64, 64), rho)
         t0 = time.perf_counter()
-        o.run(config1_steps)
-        rates[nt] = csu1 * config1_steps / (time.perf_counter() - t0)
-        print("small_configs: oracle, droplet, %d steps on %d thread(s)" % (config1_steps, nt),
+        o.run(droplet_steps)
+        rates[nt] = csu1 * droplet_steps / (time.perf_counter() - t0)
+        print("small_workloads: oracle, droplet, %d steps on %d thread(s)" % (droplet_steps, nt),
               file=sys.stderr, flush=True)
-    out["config1_droplet64"] = dict(
-        gpu=dict(steps=config1_steps, steps_per_s=round(config1_steps / g, 1),
-                 csu_s=round(csu1 * config1_steps / g, 1)),
-        oracle=dict(sample="%d steps (the full run)" % config1_steps,
+    out["droplet64_c1c3nc5"] = dict(
+        gpu=dict(steps=droplet_steps, steps_per_s=round(droplet_steps / g, 1),
+                 csu_s=round(csu1 * droplet_steps / g, 1)),
+        oracle=dict(sample="%d steps (the full run)" % droplet_steps,
                     csu_s_all_cores=round(rates[threads], 1),
                     csu_s_one_thread=round(rates[1], 1)))
-    # config 2
+    # the Table II slabs
     c2, c2_1, c2_wall = [], [], []
     for case in range(1, 7):
         comps, T, _ = C.table_ii_components(case)
@@ -434,23 +433,23 @@ def small_configs_leg(config1_steps=2000, config2_steps=20000, window=200, sweep
         set_threads(threads)
         o = OracleLBM(oracle_mixture(comps, T), 0, (256, 32), rho2)
         t0 = time.perf_counter()
-        o.run(config2_steps)
+        o.run(slab_steps)
         dt = time.perf_counter() - t0
-        c2.append(round(csu2 * config2_steps / dt, 1))
+        c2.append(round(csu2 * slab_steps / dt, 1))
         c2_wall.append(round(dt, 2))
-        print("small_configs: oracle, Table II case %d, %d steps in %.1f s"
-              % (case, config2_steps, dt), file=sys.stderr, flush=True)
+        print("small_workloads: oracle, Table II case %d, %d steps in %.1f s"
+              % (case, slab_steps, dt), file=sys.stderr, flush=True)
         set_threads(1)
         o = OracleLBM(oracle_mixture(comps, T), 0, (256, 32), rho2)
         t0 = time.perf_counter()
         o.run(window)
         c2_1.append(round(csu2 * window / (time.perf_counter() - t0), 1))
     set_threads(threads)
-    out["config2_vle_256x32"] = dict(
+    out["table_ii_slabs_256x32"] = dict(
         N=[1, 2, 3, 4, 5, 6], oracle_csu_s_all_cores=c2, oracle_wall_s_all_cores=c2_wall,
-        sample_all_cores="%d steps per case (the full run)" % config2_steps,
+        sample_all_cores="%d steps per case (the full run)" % slab_steps,
         oracle_csu_s_one_thread=c2_1, sample_one_thread="%d steps per case" % window)
-    # config 3
+    # the ternary sweep instances
     from paper_2306_10652_amd import batch
     specs = batch.ternary_specs(S["ternary_sweep"])
     csu = 0
@@ -462,7 +461,7 @@ def small_configs_leg(config1_steps=2000, config2_steps=20000, window=200, sweep
         el += time.perf_counter() - t0
         csu += 3 * sp["shape"][0] * sp["shape"][1] * sweep_window
         del o
-    out["config3_sweep"] = dict(instances=len(specs), oracle_csu_s_all_cores=round(csu / el, 1),
+    out["ternary_sweep_256"] = dict(instances=len(specs), oracle_csu_s_all_cores=round(csu / el, 1),
                                 sample="%d steps of each instance" % sweep_window)
     set_threads(threads)
     return out
@@ -668,7 +667,8 @@ def main():
     ap.add_argument("--legs", default="sweep,time_vs_n,serving,d3q19",
                     help="comma-separated extra legs to run (sweep, time_vs_n, serving, "
                          "d3q19; serving_more, the serving stream over more requests, and "
-                         "small_configs, the oracle on configurations 1-3 beside the GPU, "
+                         "small_workloads, the oracle beside the GPU on the 64^2 droplet, the "
+                         "Table II slabs and the sweep instances, "
                          "run only when named)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both",
                     help="restrict the GPU legs (profiling runs)")
@@ -780,8 +780,8 @@ def main():
         out["serving"] = serving_leg()
     if "d3q19" in legs:
         out["d3q19"] = d3q19_leg()
-    if "small_configs" in legs:
-        out["small_configs"] = small_configs_leg()
+    if "small_workloads" in legs:
+        out["small_workloads"] = small_workloads_leg()
     if "serving_more" in legs:
         out["serving_more"] = serving_leg(count=20, largest=("D2Q9", "D3Q19"))
     if not args.no_cpu:
