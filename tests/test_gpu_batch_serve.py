@@ -113,13 +113,15 @@ def test_fp32_sweep_instances_bulk_phases_at_equilibrium():
     sizes = [sp["shape"][0] for sp in specs]
     pick = [sizes.index(n) for n in sorted(set(sizes))[:8]]
     sel = [specs[k] for k in pick]
-    a = batch.Sweep(sel, capi.FP32_STORAGE)
-    b = batch.Sweep(sel, capi.FP64)
+    import torch
+    a = batch.Sweep(sel, capi.FP32_STORAGE, stream=torch.cuda.Stream())
+    b = batch.Sweep(sel, capi.FP64, stream=torch.cuda.Stream())
+    # the two precisions side by side, one stream each
+    W.run_side_by_side([a.step, b.step], 1900000)
     for sw in (a, b):
-        sw.step(1900000)
         for s in sw.sims:
             s.diagnostics()
-        sw.step(100000)
+    W.run_side_by_side([a.step, b.step], 100000)
     worst_rho, worst_x, compared, worst_res = 0.0, 0.0, 0, 0.0
     for sa, sb, sp in zip(a.sims, b.sims, sel):
         worst_res = max(worst_res, sa.diagnostics()["residual"], sb.diagnostics()["residual"])

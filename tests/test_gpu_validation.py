@@ -93,6 +93,7 @@ def test_vle_cases_1_to_6_reproduce_tables_iii_and_iv():
         t3 = json.load(f)["cases"]
     with open(os.path.join(gold, "table_iv.json")) as f:
         t4 = json.load(f)["cases"]
+    import torch
     n = 400
     runs = []
     for case in range(1, 7):
@@ -100,9 +101,11 @@ def test_vle_cases_1_to_6_reproduce_tables_iii_and_iv():
         st = W.states()["vle%d" % case]
         mix = capi.Mixture.from_components(comps, T)
         sim = capi.Simulation(mix, capi.D2Q9, capi.FP64, (n, 2),
-                              Fi.slab(n, 2, st["rho_V"], st["rho_L"], st["S_V"]))
+                              Fi.slab(n, 2, st["rho_V"], st["rho_L"], st["S_V"]),
+                              stream=torch.cuda.Stream())
         runs.append((case, comps, T, mix, sim))
-    capi.step_many([r[4] for r in runs], 1000000)
+    # the six cases side by side, one stream each
+    W.run_side_by_side([r[4].step_n for r in runs], 1000000)
     worst_t3_rho = worst_t3_x = worst_t4 = 0.0
     for case, comps, T, mix, sim in runs:
         assert sim.diagnostics()["rc"] == 0
@@ -298,7 +301,7 @@ def test_young_laplace_linear_in_inverse_radius():
 def test_young_laplace_paper_setup_and_kappa_scaling():
     """Section III.A as set up in the paper: C1/C2/C3 (Table I, k_ij = 0)
     flashed at 250 K and 50 bar (z = 0.5, 0.25, 0.25), drops of initial
-    radius 20, 30, 40, 50 on 200 x 200, 10^6 steps (all four drops of one
+    radius 20, 30, 40, 50 on 200 x 200, 10^6 steps (the drops of both
     kappa_ref in one batched launch per step, FP64).  For kappa_ref = 0.02
     and 0.04: Delta p (EOS pressures of 4 x 4 windows at the drop's centre
     of mass and farthest from it) is linear in 1 / R_e (equimolar radius)
@@ -315,13 +318,16 @@ def test_young_laplace_paper_setup_and_kappa_scaling():
     comps_c = [C.TABLE_I["C1"], C.TABLE_I["C2"], C.TABLE_I["C3"]]
     n = 200
     sig = {}
+    sweeps = {}
     for kref in (0.02, 0.04):
-        om = oracle_mixture(comps_c, 250.0, kappa_ref=kref)
         specs = [dict(comps=comps, T=250.0, kij=None, shape=(n, n),
                       rho=Fi.droplet(n, n, st["rho_L"], st["rho_V"], R))
                  for R in (20.0, 30.0, 40.0, 50.0)]
-        sw = batch.Sweep(specs, capi.FP64, kappa_ref=kref)
-        sw.step(1000000)
+        sweeps[kref] = batch.Sweep(specs, capi.FP64, kappa_ref=kref)
+    # all eight drops (both kappa_ref) in one batched launch per step
+    capi.step_many(sweeps[0.02].sims + sweeps[0.04].sims, 1000000)
+    for kref, sw in sweeps.items():
+        om = oracle_mixture(comps_c, 250.0, kappa_ref=kref)
         inv_R, dp = [], []
         for sim in sw.sims:
             assert sim.diagnostics()["rc"] == 0

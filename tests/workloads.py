@@ -91,3 +91,16 @@ def random_droplet(N, shape, seed, lattice=0, noise=1e-2, eos="PR"):
     rho = Fi.add_noise(rho, noise, seed)
     return Workload(comps, 300.0, rho, (nx, ny, nz) if lattice else (nx, ny), lattice=lattice,
                     eos=eos)
+
+
+def run_side_by_side(steppers, nsteps, chunk=3000):
+    """Advance independent runs, each stepping on its own stream, by nsteps
+    each, enqueued in turns of `chunk` steps so that every stream has work
+    queued at once (small grids leave most of the GPU idle: their launches
+    then overlap).  steppers: callables step(n) that enqueue n steps."""
+    done = 0
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        for step in steppers:
+            step(k)
+        done += k
