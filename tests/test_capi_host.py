@@ -36,6 +36,27 @@ def test_header_and_library_export_the_same_functions():
         assert hasattr(L, n), n
 
 
+def test_header_is_plain_c(tmp_path):
+    """The boundary is a C ABI: the header compiles as strict C99 (no C++
+    constructs, no torch or HIP types) and declares every entry point with
+    C linkage for a C++ caller."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "fuglbm.h"\nint main(void) { fuglbm_diag d; '
+                   'const char *(*f)(void) = fuglbm_last_error; (void)d; return f == 0; }\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                        "-I", os.path.dirname(HEADER), "-c", str(src), "-o",
+                        str(tmp_path / "use.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    text = open(HEADER).read()
+    assert 'extern "C"' in text and "hip" not in re.sub(r"/\*.*?\*/", "", text, flags=re.S).replace(
+        "hip_stream", "")
+
+
 # heavy pseudo-components: PR's alpha branch for omega > 0.49, and the
 # split itself (omega = 0.49 takes the first branch on both sides)
 HEAVY = [C.TABLE_I["C1"], C.Component("h049", 600.0, 20.0, 0.49, 180.0),
